@@ -1,0 +1,201 @@
+/*
+ * fdk.h -- C ABI of the MI355X (gfx950) voxel-driven FDK backprojection library.
+ *
+ * The operation (Hofmann et al., "Performance Engineering for a Medical Imaging
+ * Application on the Intel Xeon Phi Accelerator", Sec. "RabbitCT Benchmarking
+ * Framework", Listing 1 and the text after it):
+ *
+ *   for every voxel (x, y, z) of an L^3 grid and every projection k:
+ *     X          = O + (x, y, z) * MM           voxel centre in world coordinates (mm)
+ *     (u, v, w)  = A_k (X, 1)                   3x4 projection matrix of projection k
+ *     val        = bilinear sample of I_k at (u/w, v/w), zero off the detector
+ *     V(x, y, z) += val / w^2                   inverse-square weight
+ *
+ * with floor() for the integer part of the detector coordinates, a tap (i, j)
+ * on the detector iff 0 <= i < width and 0 <= j < height, pixel (i, j) centred
+ * on integer coordinates, and zero applied per tap.
+ *
+ * Layouts (all row-major, C order):
+ *   volume      float32, index ((z - z_begin) * L + y) * L + x  (x fastest)
+ *   projections [n_proj][height][width], column index (u) fastest
+ *   matrices    float64, 12 per projection, A[r][c] at r * 4 + c.  (The paper's
+ *               listing indexes the same matrix column-major, A[r + 3c].)
+ *
+ * Ownership and concurrency:
+ *   - the caller owns every buffer; the library never frees or retains them;
+ *   - host arrays (matrices, descriptors) are read before the call returns;
+ *   - device pointers belong to the current HIP device;
+ *   - work is enqueued on the given HIP stream (NULL = the null stream) and
+ *     the call returns without waiting; results are valid once the stream has
+ *     been synchronised;
+ *   - the library keeps one device workspace per device (projection staging,
+ *     coefficient tables, counters).  Calls issued on different streams of one
+ *     device are ordered by the library (a call on a new stream first waits for
+ *     the previous stream's work to finish) so they never share workspace
+ *     concurrently.
+ *
+ * Errors: every argument is validated on the host before anything is
+ * enqueued; on error nothing is enqueued, outputs are untouched, the status is
+ * returned and fdk_last_error() (thread-local) holds a description.
+ */
+#ifndef FDK_H
+#define FDK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDK_ABI_VERSION 1
+
+typedef enum fdk_status {
+    FDK_OK = 0,
+    FDK_E_INVALID_ARG = -1,  /* null pointer, bad size, non-finite geometry, overflow */
+    FDK_E_GEOMETRY = -2,     /* w <= 0 at a corner voxel of the processed region */
+    FDK_E_UNSUPPORTED = -3,  /* unknown dtype, device is not gfx950 */
+    FDK_E_NOMEM = -4,        /* workspace allocation failed */
+    FDK_E_DEVICE = -5        /* a HIP runtime call failed */
+} fdk_status;
+
+typedef enum fdk_dtype {
+    FDK_F32 = 0,   /* IEEE binary32 */
+    FDK_F16 = 1,   /* IEEE binary16 */
+    FDK_BF16 = 2   /* bfloat16 */
+} fdk_dtype;
+
+/* The volume grid (paper: edge L, voxel pitch MM, origin O).  The buffer
+ * passed with it holds the planes [z_begin, z_begin + z_count), which lets a
+ * large volume be processed as z-slabs. */
+typedef struct fdk_volume {
+    int32_t L;             /* voxels per edge, 1 .. 32768 */
+    int32_t z_begin;       /* first plane held by the buffer, 0 <= z_begin < L */
+    int32_t z_count;       /* planes held, 1 <= z_count <= L - z_begin */
+    int32_t reserved;      /* must be 0 */
+    double voxel_mm;       /* voxel pitch MM > 0 */
+    double origin_mm[3];   /* world position (mm) of the centre of voxel (0, 0, 0) */
+} fdk_volume;
+
+/* A projection stack: one 3x4 matrix and one width x height image per
+ * projection.  For FDK_F16 / FDK_BF16 data the stored value of projection k is
+ * p / scale[k] (see fdk_pack_projections); the library multiplies it back.
+ * fdk_forwardproject uses only n_proj, width, height and mats. */
+typedef struct fdk_projections {
+    int32_t n_proj;        /* N >= 1 */
+    int32_t width;         /* W >= 1, row length (u, fastest) */
+    int32_t height;        /* H >= 1, rows (v) */
+    int32_t dtype;         /* fdk_dtype of data */
+    const double* mats;    /* HOST, n_proj * 12 float64, row-major per projection */
+    const void* data;      /* DEVICE, [n_proj][height][width] of dtype */
+    const float* scale;    /* DEVICE, n_proj float32 dequantisation factors, or NULL for 1 */
+} fdk_projections;
+
+/* One scan of a batch. */
+typedef struct fdk_scan {
+    fdk_volume vol;
+    fdk_projections proj;
+    float* volume;         /* DEVICE output, z_count * L * L float32 */
+} fdk_scan;
+
+/*
+ * Backprojection (the paper's Listing 1, all projections in one call):
+ * volume[v] = (accumulate ? volume[v] : 0) + sum_k val_k(v) / w_k(v)^2.
+ * Defined by: Sec. "RabbitCT Benchmarking Framework", Listing 1; the paper's
+ * zero-padding and clipping optimisations (Sec. "Implementation") change only
+ * how it is computed.
+ *   vol        grid description (host)
+ *   proj       projection stack (host struct; data and scale on the device)
+ *   volume     DEVICE, z_count * L * L float32, written (or added to)
+ *   accumulate 0: overwrite, 1: add to the existing contents
+ *   stream     hipStream_t or NULL
+ * FDK_E_GEOMETRY if w <= 0 at any corner voxel of the processed planes for any
+ * projection (w is affine in the voxel position, so this covers the region).
+ */
+fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj,
+                           float* volume, int accumulate, void* stream);
+
+/*
+ * Voxel-driven forward projection, the exact adjoint B^T of fdk_backproject
+ * (the transpose of the linear map of Listing 1): for every voxel v and
+ * projection k the value volume[v] / w^2 is scattered onto the four bilinear
+ * taps that lie on the detector, with the bilinear weights of the sample the
+ * backprojection would take there.
+ *   vol        grid description (host)
+ *   volume     DEVICE, z_count * L * L float32 input
+ *   geom       n_proj, width, height, mats (data, dtype, scale are ignored)
+ *   proj_out   DEVICE, n_proj * height * width float32, written (or added to)
+ *   accumulate 0: overwrite, 1: add
+ *   stream     hipStream_t or NULL
+ * Accumulation uses float atomics: the result is deterministic only up to
+ * FP32 rounding order.
+ */
+fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume,
+                              const fdk_projections* geom, float* proj_out,
+                              int accumulate, void* stream);
+
+/*
+ * Many independent backprojections (scans of uneven size, each with its own
+ * grid, projections, matrices and output) in one persistent launch that pulls
+ * (scan, tile) work items from a queue.  The launch sequence is captured once
+ * into a HIP graph, cached by the content of the descriptors (pointers, sizes,
+ * matrices, scales), and replayed on later calls with the same content.
+ * Same per-scan semantics and errors as fdk_backproject; a failing scan's
+ * index is reported by fdk_last_error().
+ *   scans      HOST array of n_scans descriptors
+ *   n_scans    1 .. 4096
+ */
+fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans,
+                                   int accumulate, void* stream);
+
+/*
+ * Projection storage conversion (FP32 -> FP16 or BF16) with a per-projection
+ * scale: scale_out[k] = max_ij |src[k][j][i]| / 2^14 (1 if the projection is
+ * all zero), dst[k][j][i] = round_to_nearest_even(src / scale_out[k]).
+ *   src        DEVICE, n_proj * height * width float32
+ *   dtype      FDK_F16 or FDK_BF16
+ *   dst        DEVICE, n_proj * height * width 16-bit values
+ *   scale_out  DEVICE, n_proj float32
+ */
+fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width,
+                                int32_t height, int32_t dtype, void* dst,
+                                float* scale_out, void* stream);
+
+/* Tile shape of the backprojection kernel: each lane of a 64-wide wavefront
+ * owns one x column and a strip of `strip` voxels along y; a workgroup stacks
+ * `waves` wavefronts along z.  strip in {2, 4, 8, 16}, waves in {1, 2, 4}.
+ * fdk_set_tile pins the shape for a dtype (0, 0 restores automatic choice from
+ * the tuning table); fdk_get_tile reports the shape a call with this grid and
+ * dtype would use. */
+fdk_status fdk_set_tile(int32_t dtype, int32_t strip, int32_t waves);
+fdk_status fdk_get_tile(const fdk_volume* vol, int32_t dtype, int32_t* strip,
+                        int32_t* waves);
+
+/* Tuning table: entries (dtype, size class) -> tile shape, as written by the
+ * autotuner.  fdk_load_tuning reads a file of lines "dtype class strip waves"
+ * ('#' starts a comment); size class = floor(log2(L)).  Entries for other
+ * library ABI versions are rejected (the file's first line must read
+ * "fdk-tuning <FDK_ABI_VERSION> gfx950").  Returns the number of entries read
+ * or a negative fdk_status.  fdk_set_tuning_entry sets one entry; strip = waves
+ * = 0 removes it. */
+int32_t fdk_load_tuning(const char* path);
+fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip,
+                                int32_t waves);
+
+/* Host-side check of a call's arguments: the validation fdk_backproject
+ * performs, without touching the GPU. */
+fdk_status fdk_validate(const fdk_volume* vol, const fdk_projections* proj,
+                        int need_data);
+
+/* Releases the calling thread's current-device workspace and cached graphs
+ * (waits for the device first). */
+fdk_status fdk_release_workspace(void);
+
+const char* fdk_status_string(fdk_status status);
+const char* fdk_last_error(void);   /* thread-local, "" if none */
+int32_t fdk_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDK_H */

@@ -1,0 +1,330 @@
+"""Python binding of the gfx950 FDK backprojection library (libfdk.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/fdk.h.  PyTorch supplies device
+memory (tensors) and streams.  If the compiled library is missing, every call
+raises; there is no CPU fallback.
+
+Conventions: projection matrices are (N, 3, 4) float64 row-major, projections
+(N, H, W) with the column index fastest, volumes (nz, L, L) indexed (z, y, x).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # loads the HIP runtime that libfdk.so binds to
+
+from . import _build
+
+__all__ = [
+    "FdkError", "Volume", "Geometry", "F32", "F16", "BF16", "load", "backproject",
+    "forwardproject", "backproject_batched", "pack_projections", "set_tile", "get_tile",
+    "load_tuning", "set_tuning_entry", "validate", "release_workspace", "abi_version",
+    "BackProject", "ForwardProject", "Scan",
+]
+
+F32, F16, BF16 = 0, 1, 2
+_TORCH_DTYPE = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+
+
+class FdkError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_status_name(status)}: {message}")
+        self.status = status
+
+
+class _Volume(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("z_begin", ctypes.c_int32), ("z_count", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("voxel_mm", ctypes.c_double),
+                ("origin_mm", ctypes.c_double * 3)]
+
+
+class _Proj(ctypes.Structure):
+    _fields_ = [("n_proj", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("mats", ctypes.POINTER(ctypes.c_double)),
+                ("data", ctypes.c_void_p), ("scale", ctypes.c_void_p)]
+
+
+class _Scan(ctypes.Structure):
+    _fields_ = [("vol", _Volume), ("proj", _Proj), ("volume", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load libfdk.so from the package directory (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB):
+        raise FdkError(-3, f"HIP library not built: {_build.LIB} is missing "
+                           "(run __graft_entry__.build())")
+    lib = ctypes.CDLL(_build.LIB)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    pv, pp, ps = ctypes.POINTER(_Volume), ctypes.POINTER(_Proj), ctypes.POINTER(_Scan)
+    sig = {
+        "fdk_backproject": ([pv, pp, vp, ctypes.c_int, vp], ctypes.c_int),
+        "fdk_forwardproject": ([pv, vp, pp, vp, ctypes.c_int, vp], ctypes.c_int),
+        "fdk_backproject_batched": ([ps, i32, ctypes.c_int, vp], ctypes.c_int),
+        "fdk_pack_projections": ([vp, i32, i32, i32, i32, vp, vp, vp], ctypes.c_int),
+        "fdk_set_tile": ([i32, i32, i32], ctypes.c_int),
+        "fdk_get_tile": ([pv, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
+        "fdk_load_tuning": ([ctypes.c_char_p], i32),
+        "fdk_set_tuning_entry": ([i32, i32, i32, i32], ctypes.c_int),
+        "fdk_validate": ([pv, pp, ctypes.c_int], ctypes.c_int),
+        "fdk_release_workspace": ([], ctypes.c_int),
+        "fdk_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "fdk_last_error": ([], ctypes.c_char_p),
+        "fdk_abi_version": ([], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _status_name(st: int) -> str:
+    names = {0: "FDK_OK", -1: "FDK_E_INVALID_ARG", -2: "FDK_E_GEOMETRY", -3: "FDK_E_UNSUPPORTED",
+             -4: "FDK_E_NOMEM", -5: "FDK_E_DEVICE"}
+    return names.get(st, f"status {st}")
+
+
+def _check(st: int):
+    if st != 0:
+        raise FdkError(st, load().fdk_last_error().decode())
+
+
+@dataclass
+class Volume:
+    """L^3 grid of voxel pitch voxel_mm; origin_mm is the centre of voxel 0
+    (default: volume centred on the isocentre).  Buffers hold the planes
+    [z_begin, z_begin + z_count)."""
+    L: int
+    voxel_mm: float
+    origin_mm: Optional[Sequence[float]] = None
+    z_begin: int = 0
+    z_count: Optional[int] = None
+
+    def c(self) -> _Volume:
+        v = _Volume()
+        v.L = self.L
+        v.z_begin = self.z_begin
+        v.z_count = self.L - self.z_begin if self.z_count is None else self.z_count
+        v.reserved = 0
+        v.voxel_mm = self.voxel_mm
+        o = self.origin_mm
+        if o is None:
+            c = -(self.L - 1) * self.voxel_mm / 2.0
+            o = (c, c, c)
+        v.origin_mm[:] = [float(x) for x in o]
+        return v
+
+    @property
+    def planes(self) -> int:
+        return self.L - self.z_begin if self.z_count is None else self.z_count
+
+    def slab(self, z_begin: int, z_count: int) -> "Volume":
+        return Volume(self.L, self.voxel_mm, self.origin_mm, z_begin, z_count)
+
+
+@dataclass
+class Geometry:
+    """Projection geometry: one 3x4 matrix per projection and the detector size."""
+    mats: np.ndarray
+    width: int
+    height: int
+    _m: np.ndarray = field(init=False, repr=False)
+
+    def __post_init__(self):
+        self._m = np.ascontiguousarray(np.asarray(self.mats, dtype=np.float64).reshape(-1, 12))
+
+    @property
+    def n_proj(self) -> int:
+        return self._m.shape[0]
+
+    def c(self, data=None, dtype=F32, scale=None) -> _Proj:
+        p = _Proj()
+        p.n_proj = self.n_proj
+        p.width = self.width
+        p.height = self.height
+        p.dtype = dtype
+        p.mats = self._m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.data = data
+        p.scale = scale
+        return p
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dev_ptr(t: torch.Tensor, name: str, dtypes=None) -> int:
+    if not t.is_cuda:
+        raise FdkError(-1, f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise FdkError(-1, f"{name} must be contiguous")
+    if dtypes is not None and t.dtype not in dtypes:
+        raise FdkError(-3, f"{name} has dtype {t.dtype}")
+    return t.data_ptr()
+
+
+def backproject(proj: torch.Tensor, geom: Geometry, vol: Volume, out: torch.Tensor = None,
+                accumulate: bool = False, scale: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """fdk_backproject: volume (z_count, L, L) float32 from projections (N, H, W)."""
+    lib = load()
+    if proj.dtype not in _TORCH_DTYPE:
+        raise FdkError(-3, f"projection dtype {proj.dtype}")
+    if tuple(proj.shape) != (geom.n_proj, geom.height, geom.width):
+        raise FdkError(-1, f"projections {tuple(proj.shape)} do not match geometry "
+                           f"{(geom.n_proj, geom.height, geom.width)}")
+    if out is None:
+        out = torch.empty((vol.planes, vol.L, vol.L), dtype=torch.float32, device=proj.device)
+    elif tuple(out.shape) != (vol.planes, vol.L, vol.L) or out.dtype != torch.float32:
+        raise FdkError(-1, "output volume has the wrong shape or dtype")
+    sp = None
+    if scale is not None:
+        if scale.numel() != geom.n_proj:
+            raise FdkError(-1, "scale must have one entry per projection")
+        sp = _dev_ptr(scale, "scale", (torch.float32,))
+    v = vol.c()
+    p = geom.c(_dev_ptr(proj, "projections"), _TORCH_DTYPE[proj.dtype], sp)
+    _check(lib.fdk_backproject(ctypes.byref(v), ctypes.byref(p),
+                               _dev_ptr(out, "volume", (torch.float32,)), int(bool(accumulate)),
+                               _stream(stream)))
+    return out
+
+
+def forwardproject(volume: torch.Tensor, geom: Geometry, vol: Volume, out: torch.Tensor = None,
+                   accumulate: bool = False, stream=None) -> torch.Tensor:
+    """fdk_forwardproject (adjoint of backproject): projections (N, H, W) float32."""
+    lib = load()
+    if tuple(volume.shape) != (vol.planes, vol.L, vol.L):
+        raise FdkError(-1, f"volume {tuple(volume.shape)} does not match the grid")
+    if out is None:
+        out = torch.empty((geom.n_proj, geom.height, geom.width), dtype=torch.float32,
+                          device=volume.device)
+    elif tuple(out.shape) != (geom.n_proj, geom.height, geom.width) or out.dtype != torch.float32:
+        raise FdkError(-1, "output projections have the wrong shape or dtype")
+    v = vol.c()
+    p = geom.c()
+    _check(lib.fdk_forwardproject(ctypes.byref(v), _dev_ptr(volume, "volume", (torch.float32,)),
+                                  ctypes.byref(p), _dev_ptr(out, "projections", (torch.float32,)),
+                                  int(bool(accumulate)), _stream(stream)))
+    return out
+
+
+@dataclass
+class Scan:
+    proj: torch.Tensor
+    geom: Geometry
+    vol: Volume
+    out: torch.Tensor
+    scale: Optional[torch.Tensor] = None
+
+
+def backproject_batched(scans: Sequence[Scan], accumulate: bool = False, stream=None) -> None:
+    """fdk_backproject_batched: all scans in one persistent launch (HIP graph)."""
+    lib = load()
+    arr = (_Scan * len(scans))()
+    for i, s in enumerate(scans):
+        if s.proj.dtype not in _TORCH_DTYPE:
+            raise FdkError(-3, f"scan {i}: projection dtype {s.proj.dtype}")
+        if tuple(s.proj.shape) != (s.geom.n_proj, s.geom.height, s.geom.width):
+            raise FdkError(-1, f"scan {i}: projections do not match geometry")
+        if tuple(s.out.shape) != (s.vol.planes, s.vol.L, s.vol.L) or s.out.dtype != torch.float32:
+            raise FdkError(-1, f"scan {i}: output volume has the wrong shape or dtype")
+        arr[i].vol = s.vol.c()
+        sp = _dev_ptr(s.scale, "scale", (torch.float32,)) if s.scale is not None else None
+        arr[i].proj = s.geom.c(_dev_ptr(s.proj, "projections"), _TORCH_DTYPE[s.proj.dtype], sp)
+        arr[i].volume = _dev_ptr(s.out, "volume", (torch.float32,))
+    _check(lib.fdk_backproject_batched(arr, len(scans), int(bool(accumulate)), _stream(stream)))
+
+
+def pack_projections(proj: torch.Tensor, dtype=torch.float16, stream=None):
+    """fdk_pack_projections: (packed (N, H, W) float16/bfloat16, scale (N,) float32)."""
+    lib = load()
+    if proj.dtype != torch.float32 or proj.dim() != 3:
+        raise FdkError(-1, "pack_projections expects (N, H, W) float32")
+    code = {torch.float16: F16, torch.bfloat16: BF16}.get(dtype)
+    if code is None:
+        raise FdkError(-3, f"pack dtype {dtype}")
+    n, h, w = proj.shape
+    packed = torch.empty((n, h, w), dtype=dtype, device=proj.device)
+    scale = torch.empty(n, dtype=torch.float32, device=proj.device)
+    _check(lib.fdk_pack_projections(_dev_ptr(proj, "projections"), n, w, h, code,
+                                    packed.data_ptr(), scale.data_ptr(), _stream(stream)))
+    return packed, scale
+
+
+def set_tile(dtype: int, strip: int, waves: int) -> None:
+    _check(load().fdk_set_tile(dtype, strip, waves))
+
+
+def get_tile(vol: Volume, dtype: int = F32) -> tuple[int, int]:
+    s, w = ctypes.c_int32(), ctypes.c_int32()
+    v = vol.c()
+    _check(load().fdk_get_tile(ctypes.byref(v), dtype, ctypes.byref(s), ctypes.byref(w)))
+    return s.value, w.value
+
+
+def load_tuning(path: str) -> int:
+    n = load().fdk_load_tuning(path.encode())
+    if n < 0:
+        _check(n)
+    return n
+
+
+def set_tuning_entry(dtype: int, size_class: int, strip: int, waves: int) -> None:
+    _check(load().fdk_set_tuning_entry(dtype, size_class, strip, waves))
+
+
+def validate(geom: Geometry, vol: Volume, need_data: bool = False, dtype: int = F32) -> None:
+    """Host-side argument check (no GPU work); raises FdkError."""
+    v = vol.c()
+    p = geom.c(1 if need_data else None, dtype)
+    _check(load().fdk_validate(ctypes.byref(v), ctypes.byref(p), int(need_data)))
+
+
+def release_workspace() -> None:
+    _check(load().fdk_release_workspace())
+
+
+def abi_version() -> int:
+    return int(load().fdk_abi_version())
+
+
+class BackProject(torch.autograd.Function):
+    """V = B p.  Gradient with respect to p: B^T grad_V (the forward projector)."""
+
+    @staticmethod
+    def forward(ctx, proj, geom: Geometry, vol: Volume):
+        ctx.geom, ctx.vol = geom, vol
+        return backproject(proj.contiguous(), geom, vol)
+
+    @staticmethod
+    def backward(ctx, grad_v):
+        g = forwardproject(grad_v.contiguous().to(torch.float32), ctx.geom, ctx.vol)
+        return g, None, None
+
+
+class ForwardProject(torch.autograd.Function):
+    """p = B^T V.  Gradient with respect to V: B grad_p (the backprojector)."""
+
+    @staticmethod
+    def forward(ctx, volume, geom: Geometry, vol: Volume):
+        ctx.geom, ctx.vol = geom, vol
+        return forwardproject(volume.contiguous(), geom, vol)
+
+    @staticmethod
+    def backward(ctx, grad_p):
+        g = backproject(grad_p.contiguous().to(torch.float32), ctx.geom, ctx.vol)
+        return g, None, None

@@ -1,0 +1,846 @@
+// Host layer of the FDK backprojection library: argument validation, FP64
+// matrix composition, workspace management, tile selection, launches, and the
+// HIP-graph cache of the batched form.  Implements include/fdk.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fdk.h"
+#include "fdk_internal.h"
+
+using namespace fdk;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fdk_status fail(fdk_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(FDK_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+constexpr int kMaxL = 32768;
+constexpr int kMaxScans = 4096;
+
+int esize_of(int dtype) { return dtype == FDK_F32 ? 4 : 2; }
+
+// ------------------------------------------------------------------ validation
+fdk_status check_volume(const fdk_volume* v)
+{
+    if (v == nullptr) return fail(FDK_E_INVALID_ARG, "volume descriptor is NULL");
+    if (v->L < 1 || v->L > kMaxL) return fail(FDK_E_INVALID_ARG, "L=%d outside [1, %d]", v->L, kMaxL);
+    if (v->z_begin < 0 || v->z_begin >= v->L)
+        return fail(FDK_E_INVALID_ARG, "z_begin=%d outside [0, L)", v->z_begin);
+    if (v->z_count < 1 || v->z_count > v->L - v->z_begin)
+        return fail(FDK_E_INVALID_ARG, "z_count=%d outside [1, L - z_begin]", v->z_count);
+    if (v->reserved != 0) return fail(FDK_E_INVALID_ARG, "reserved field must be 0");
+    if (!std::isfinite(v->voxel_mm) || !(v->voxel_mm > 0.0))
+        return fail(FDK_E_INVALID_ARG, "voxel_mm must be finite and > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(v->origin_mm[a])) return fail(FDK_E_INVALID_ARG, "origin_mm is not finite");
+    return FDK_OK;
+}
+
+fdk_status check_proj(const fdk_projections* p, bool need_data)
+{
+    if (p == nullptr) return fail(FDK_E_INVALID_ARG, "projection descriptor is NULL");
+    if (p->n_proj < 1) return fail(FDK_E_INVALID_ARG, "n_proj=%d < 1", p->n_proj);
+    if (p->width < 1 || p->height < 1)
+        return fail(FDK_E_INVALID_ARG, "detector %dx%d has an empty axis", p->width, p->height);
+    if (p->mats == nullptr) return fail(FDK_E_INVALID_ARG, "mats is NULL");
+    if (need_data) {
+        if (p->dtype != FDK_F32 && p->dtype != FDK_F16 && p->dtype != FDK_BF16)
+            return fail(FDK_E_UNSUPPORTED, "unknown dtype %d", p->dtype);
+        if (p->data == nullptr) return fail(FDK_E_INVALID_ARG, "projection data is NULL");
+    }
+    const int es = need_data ? esize_of(p->dtype) : 4;
+    const int64_t wp = (int64_t)p->width + kPadLo + kPadHi;
+    const int64_t hp = (int64_t)p->height + kPadLo + kPadHi;
+    // staged image offsets are signed 32-bit, row pitch a 24-bit multiplier
+    if (wp * hp * es >= (int64_t(1) << 31) || wp >= (int64_t(1) << 23) || hp >= (int64_t(1) << 23))
+        return fail(FDK_E_INVALID_ARG, "detector %dx%d too large", p->width, p->height);
+    if ((int64_t)p->n_proj * wp * hp * es > (int64_t(1) << 46))
+        return fail(FDK_E_INVALID_ARG, "projection stack too large");
+    for (int64_t i = 0; i < (int64_t)p->n_proj * 12; ++i)
+        if (!std::isfinite(p->mats[i])) return fail(FDK_E_INVALID_ARG, "matrix %lld has a non-finite entry", (long long)(i / 12));
+    return FDK_OK;
+}
+
+// w > 0 at the eight corner voxel centres of the processed planes, for every
+// projection.  w is affine in the voxel position, so this covers the region.
+fdk_status check_geometry(const fdk_volume* v, const fdk_projections* p)
+{
+    const double xs[2] = {0.0, (double)(v->L - 1)};
+    const double zs[2] = {(double)v->z_begin, (double)(v->z_begin + v->z_count - 1)};
+    for (int k = 0; k < p->n_proj; ++k) {
+        const double* A = p->mats + 12 * k;
+        for (int cx = 0; cx < 2; ++cx)
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cz = 0; cz < 2; ++cz) {
+                    const double X = v->origin_mm[0] + xs[cx] * v->voxel_mm;
+                    const double Y = v->origin_mm[1] + xs[cy] * v->voxel_mm;
+                    const double Z = v->origin_mm[2] + zs[cz] * v->voxel_mm;
+                    const double w = A[8] * X + A[9] * Y + A[10] * Z + A[11];
+                    if (!(w > 0.0))
+                        return fail(FDK_E_GEOMETRY,
+                                    "projection %d: w=%g <= 0 at corner voxel (%d,%d,%d)", k, w,
+                                    cx ? v->L - 1 : 0, cy ? v->L - 1 : 0,
+                                    cz ? v->z_begin + v->z_count - 1 : v->z_begin);
+                }
+    }
+    return FDK_OK;
+}
+
+// ------------------------------------------------------------------ composition
+// Per projection, the FP64 matrix that maps centred voxel indices
+// (x - c, y - c, z - c, 1), c = L/2, to centred detector coordinates
+// (u - cu w, v - cv w, w), cu = W/2, cv = H/2, scaled by one power of two 2^e
+// chosen so w is O(1).  The kernel's weight is then 2^-2e / w^2 and the
+// result is multiplied by out_scale = 2^2e.
+struct Composed {
+    std::vector<double> coef;  // n_proj * 12
+    float out_scale;
+};
+
+Composed compose(const fdk_volume* v, const fdk_projections* p)
+{
+    Composed c;
+    const int N = p->n_proj;
+    c.coef.resize((size_t)N * 12);
+    const int ctr = v->L / 2;
+    const double cu = (double)(p->width / 2), cv = (double)(p->height / 2);
+    double wsum = 0.0;
+    for (int k = 0; k < N; ++k) {
+        const double* A = p->mats + 12 * k;
+        double M[3][4];
+        for (int r = 0; r < 3; ++r) {
+            double t = A[r * 4 + 3];
+            for (int a = 0; a < 3; ++a) {
+                M[r][a] = A[r * 4 + a] * v->voxel_mm;
+                t += A[r * 4 + a] * (v->origin_mm[a] + ctr * v->voxel_mm);
+            }
+            M[r][3] = t;
+        }
+        for (int a = 0; a < 4; ++a) {
+            M[0][a] -= cu * M[2][a];
+            M[1][a] -= cv * M[2][a];
+        }
+        for (int r = 0; r < 3; ++r)
+            for (int a = 0; a < 4; ++a) c.coef[(size_t)k * 12 + r * 4 + a] = M[r][a];
+        wsum += std::fabs(M[2][3]);
+    }
+    const double wmean = wsum / N;
+    const int e = (wmean > 0.0 && std::isfinite(wmean)) ? -(int)std::lround(std::log2(wmean)) : 0;
+    const double s = std::ldexp(1.0, e);
+    for (double& x : c.coef) x *= s;
+    c.out_scale = (float)std::ldexp(1.0, 2 * e);
+    return c;
+}
+
+// ------------------------------------------------------------------ tiles
+struct TileShape { int strip, waves; };
+
+struct Tuning {
+    std::map<std::pair<int, int>, TileShape> table;  // (dtype, size class) -> shape
+    TileShape forced[3] = {{0, 0}, {0, 0}, {0, 0}};
+    bool env_loaded = false;
+};
+
+int size_class(int L)
+{
+    int c = 0;
+    while ((1 << (c + 1)) <= L) ++c;
+    return c;
+}
+
+TileShape default_tile(int L)
+{
+    if (L >= 256) return {16, 2};
+    if (L >= 96) return {8, 2};
+    return {4, 2};
+}
+
+// ------------------------------------------------------------------ device state
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+};
+
+hipError_t ensure(DevBuf& b, size_t bytes)
+{
+    if (b.n >= bytes && b.p != nullptr) return hipSuccess;
+    if (b.p != nullptr) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.n = 0;
+        if (e != hipSuccess) return e;
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return e;
+    }
+    b.n = want;
+    return hipSuccess;
+}
+
+void release(DevBuf& b)
+{
+    if (b.p != nullptr) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+}
+
+struct CoefEntry {
+    std::string key;
+    DevBuf buf;
+    float out_scale;
+};
+
+struct BatchEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+    DevBuf tiles, item_begin, stage, scale_ptrs, coef64, coef32, counter;
+};
+
+struct DeviceState {
+    bool init = false;
+    bool arch_ok = false;
+    int num_cus = 0;
+    std::string arch;
+    DevBuf staged, coef32, adjoint;
+    std::list<CoefEntry> coef_cache;   // most recent first
+    hipStream_t last_stream = nullptr;
+    bool have_last = false;
+    hipEvent_t done = nullptr;
+    // batched form
+    DevBuf batch_staged;
+    std::list<BatchEntry> batch_cache;
+    hipStream_t capture_stream = nullptr;
+};
+
+std::mutex g_mu;
+std::map<int, DeviceState> g_dev;
+Tuning g_tune;
+
+constexpr size_t kCoefCacheMax = 16;
+constexpr size_t kBatchCacheMax = 4;
+
+fdk_status device_state(DeviceState** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    DeviceState& d = g_dev[dev];
+    if (!d.init) {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        d.arch = prop.gcnArchName;
+        d.arch_ok = d.arch.rfind("gfx950", 0) == 0;
+        d.num_cus = prop.multiProcessorCount;
+        HIP_TRY(hipEventCreateWithFlags(&d.done, hipEventDisableTiming));
+        d.init = true;
+    }
+    if (!d.arch_ok)
+        return fail(FDK_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", dev,
+                    d.arch.c_str());
+    *out = &d;
+    return FDK_OK;
+}
+
+// Calls on a new stream wait for the previous call's work (shared workspace).
+fdk_status begin_call(DeviceState& d, hipStream_t s)
+{
+    if (d.have_last && d.last_stream != s) HIP_TRY(hipStreamWaitEvent(s, d.done, 0));
+    return FDK_OK;
+}
+
+fdk_status end_call(DeviceState& d, hipStream_t s)
+{
+    HIP_TRY(hipEventRecord(d.done, s));
+    d.last_stream = s;
+    d.have_last = true;
+    return FDK_OK;
+}
+
+std::string coef_key(const fdk_volume* v, const fdk_projections* p)
+{
+    std::string k;
+    auto put = [&k](const void* x, size_t n) { k.append(static_cast<const char*>(x), n); };
+    put(&v->L, sizeof(int32_t));
+    put(&v->voxel_mm, sizeof(double));
+    put(v->origin_mm, 3 * sizeof(double));
+    put(&p->n_proj, sizeof(int32_t));
+    put(&p->width, sizeof(int32_t));
+    put(&p->height, sizeof(int32_t));
+    put(p->mats, (size_t)p->n_proj * 12 * sizeof(double));
+    return k;
+}
+
+// Device copy of the composed FP64 coefficients, cached by geometry content.
+fdk_status coef_table(DeviceState& d, const fdk_volume* v, const fdk_projections* p, hipStream_t s,
+                      const double** dev, float* out_scale)
+{
+    std::string key = coef_key(v, p);
+    for (auto it = d.coef_cache.begin(); it != d.coef_cache.end(); ++it) {
+        if (it->key == key) {
+            d.coef_cache.splice(d.coef_cache.begin(), d.coef_cache, it);
+            *dev = static_cast<const double*>(d.coef_cache.front().buf.p);
+            *out_scale = d.coef_cache.front().out_scale;
+            return FDK_OK;
+        }
+    }
+    Composed c = compose(v, p);
+    for (double x : c.coef)
+        if (!std::isfinite((float)x))
+            return fail(FDK_E_INVALID_ARG, "composed projection matrix exceeds FP32 range");
+    if (d.coef_cache.size() >= kCoefCacheMax) {
+        HIP_TRY(hipDeviceSynchronize());
+        release(d.coef_cache.back().buf);
+        d.coef_cache.pop_back();
+    }
+    CoefEntry e;
+    e.key = std::move(key);
+    e.out_scale = c.out_scale;
+    hipError_t err = ensure(e.buf, c.coef.size() * sizeof(double));
+    if (err != hipSuccess) return fail(FDK_E_NOMEM, "coefficient table allocation failed: %s", hipGetErrorString(err));
+    err = hipMemcpyAsync(e.buf.p, c.coef.data(), c.coef.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) {
+        release(e.buf);
+        return fail(FDK_E_DEVICE, "coefficient upload failed: %s", hipGetErrorString(err));
+    }
+    d.coef_cache.push_front(std::move(e));
+    *dev = static_cast<const double*>(d.coef_cache.front().buf.p);
+    *out_scale = d.coef_cache.front().out_scale;
+    return FDK_OK;
+}
+
+TileShape pick_tile(int L, int dtype)
+{
+    const TileShape f = g_tune.forced[dtype];
+    if (f.strip > 0) return f;
+    auto it = g_tune.table.find({dtype, size_class(L)});
+    if (it != g_tune.table.end()) return it->second;
+    return default_tile(L);
+}
+
+void load_env_tuning();
+
+TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, TileShape t,
+                   const unsigned char* staged, const float* coef32, float* vol, float out_scale,
+                   int accumulate, int dtype)
+{
+    TileArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const int W = p->width, H = p->height;
+    const int Wp = W + kPadLo + kPadHi, Hp = H + kPadLo + kPadHi;
+    const int cu = W / 2, cv = H / 2;
+    a.proj = staged;
+    a.coef = coef32;
+    a.vol = vol;
+    const uint64_t img = (uint64_t)Wp * Hp * esize;
+    a.proj_stride = (img + 255) & ~uint64_t(255);
+    a.n_proj = p->n_proj;
+    a.L = v->L;
+    a.z_begin = v->z_begin;
+    a.z_count = v->z_count;
+    a.ctr = v->L / 2;
+    a.row_bytes = (uint32_t)(Wp * esize);
+    a.centre_bytes = (uint32_t)((cv + kPadLo) * Wp * esize + (cu + kPadLo) * esize);
+    a.proj_bytes = (uint32_t)img;
+    a.lo_x = (float)(-kPadLo - cu);
+    a.hi_x = (float)(W - 1 + kPadLo - cu);
+    a.lo_y = (float)(-kPadLo - cv);
+    a.hi_y = (float)(H - 1 + kPadLo - cv);
+    a.out_scale = out_scale;
+    a.accumulate = accumulate ? 1 : 0;
+    a.tiles_x = (v->L + kWave - 1) / kWave;
+    a.tiles_y = (v->L + t.strip - 1) / t.strip;
+    a.tiles_z = (v->z_count + t.waves - 1) / t.waves;
+    a.dtype = dtype;
+    return a;
+}
+
+fdk_status check_grid(const TileArgs& a)
+{
+    const int64_t nb = (int64_t)a.tiles_x * a.tiles_y * a.tiles_z;
+    if (nb > 0x7fffffffLL) return fail(FDK_E_INVALID_ARG, "volume too large for one launch");
+    return FDK_OK;
+}
+
+uint64_t staged_bytes(const fdk_projections* p, int esize)
+{
+    const uint64_t img = (uint64_t)(p->width + kPadLo + kPadHi) * (p->height + kPadLo + kPadHi) * esize;
+    return (uint64_t)p->n_proj * ((img + 255) & ~uint64_t(255));
+}
+
+StageArgs make_stage(const fdk_projections* p, int esize, unsigned char* dst, int64_t row_begin)
+{
+    StageArgs s;
+    s.src = p->data;
+    s.dst = dst;
+    s.n = p->n_proj;
+    s.W = p->width;
+    s.H = p->height;
+    s.Wp = p->width + kPadLo + kPadHi;
+    s.Hp = p->height + kPadLo + kPadHi;
+    s.esize = esize;
+    const uint64_t img = (uint64_t)s.Wp * s.Hp * esize;
+    s.proj_stride = (img + 255) & ~uint64_t(255);
+    s.row_begin = row_begin;
+    return s;
+}
+
+void load_env_tuning()
+{
+    if (g_tune.env_loaded) return;
+    g_tune.env_loaded = true;
+    const char* path = std::getenv("FDK_TUNING_FILE");
+    if (path != nullptr && *path) (void)fdk_load_tuning(path);
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int32_t fdk_abi_version(void) { return FDK_ABI_VERSION; }
+
+const char* fdk_status_string(fdk_status st)
+{
+    switch (st) {
+    case FDK_OK: return "FDK_OK";
+    case FDK_E_INVALID_ARG: return "FDK_E_INVALID_ARG";
+    case FDK_E_GEOMETRY: return "FDK_E_GEOMETRY";
+    case FDK_E_UNSUPPORTED: return "FDK_E_UNSUPPORTED";
+    case FDK_E_NOMEM: return "FDK_E_NOMEM";
+    case FDK_E_DEVICE: return "FDK_E_DEVICE";
+    }
+    return "FDK_E_UNKNOWN";
+}
+
+const char* fdk_last_error(void) { return g_last_error.c_str(); }
+
+fdk_status fdk_validate(const fdk_volume* vol, const fdk_projections* proj, int need_data)
+{
+    g_last_error.clear();
+    fdk_status st = check_volume(vol);
+    if (st != FDK_OK) return st;
+    st = check_proj(proj, need_data != 0);
+    if (st != FDK_OK) return st;
+    return check_geometry(vol, proj);
+}
+
+fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, float* volume,
+                           int accumulate, void* stream)
+{
+    fdk_status st = fdk_validate(vol, proj, 1);
+    if (st != FDK_OK) return st;
+    if (volume == nullptr) return fail(FDK_E_INVALID_ARG, "volume buffer is NULL");
+    std::lock_guard<std::mutex> lock(g_mu);
+    load_env_tuning();
+    const int es = esize_of(proj->dtype);
+    const TileShape t = pick_tile(vol->L, proj->dtype);
+    TileArgs probe = make_args(vol, proj, es, t, nullptr, nullptr, volume, 1.0f, accumulate, proj->dtype);
+    if ((st = check_grid(probe)) != FDK_OK) return st;
+
+    DeviceState* d = nullptr;
+    if ((st = device_state(&d)) != FDK_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = begin_call(*d, s)) != FDK_OK) return st;
+    hipError_t e = ensure(d->staged, staged_bytes(proj, es));
+    if (e != hipSuccess) return fail(FDK_E_NOMEM, "staging workspace: %s", hipGetErrorString(e));
+    e = ensure(d->coef32, (size_t)proj->n_proj * 16 * sizeof(float));
+    if (e != hipSuccess) return fail(FDK_E_NOMEM, "coefficient workspace: %s", hipGetErrorString(e));
+    const double* coef64 = nullptr;
+    float out_scale = 1.0f;
+    if ((st = coef_table(*d, vol, proj, s, &coef64, &out_scale)) != FDK_OK) return st;
+
+    StageArgs sa = make_stage(proj, es, static_cast<unsigned char*>(d->staged.p), 0);
+    HIP_TRY(launch_stage(sa, s));
+    HIP_TRY(launch_fold_single(coef64, proj->scale, static_cast<float*>(d->coef32.p), proj->n_proj, s));
+    TileArgs a = make_args(vol, proj, es, t, static_cast<unsigned char*>(d->staged.p),
+                           static_cast<float*>(d->coef32.p), volume, out_scale, accumulate, proj->dtype);
+    HIP_TRY(launch_bp(a, t.strip, t.waves, s));
+    return end_call(*d, s);
+}
+
+fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const fdk_projections* geom,
+                              float* proj_out, int accumulate, void* stream)
+{
+    fdk_status st = fdk_validate(vol, geom, 0);
+    if (st != FDK_OK) return st;
+    if (volume == nullptr) return fail(FDK_E_INVALID_ARG, "volume buffer is NULL");
+    if (proj_out == nullptr) return fail(FDK_E_INVALID_ARG, "projection output is NULL");
+    std::lock_guard<std::mutex> lock(g_mu);
+    load_env_tuning();
+    const TileShape t = pick_tile(vol->L, FDK_F32);
+    TileArgs probe = make_args(vol, geom, 4, t, nullptr, nullptr, nullptr, 1.0f, 0, FDK_F32);
+    if ((st = check_grid(probe)) != FDK_OK) return st;
+
+    DeviceState* d = nullptr;
+    if ((st = device_state(&d)) != FDK_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = begin_call(*d, s)) != FDK_OK) return st;
+    const uint64_t bytes = staged_bytes(geom, 4);
+    hipError_t e = ensure(d->adjoint, bytes);
+    if (e != hipSuccess) return fail(FDK_E_NOMEM, "adjoint workspace: %s", hipGetErrorString(e));
+    e = ensure(d->coef32, (size_t)geom->n_proj * 16 * sizeof(float));
+    if (e != hipSuccess) return fail(FDK_E_NOMEM, "coefficient workspace: %s", hipGetErrorString(e));
+    const double* coef64 = nullptr;
+    float out_scale = 1.0f;
+    if ((st = coef_table(*d, vol, geom, s, &coef64, &out_scale)) != FDK_OK) return st;
+
+    HIP_TRY(launch_fill(static_cast<float*>(d->adjoint.p), bytes / 4, 0.0f, s));
+    HIP_TRY(launch_fold_single(coef64, nullptr, static_cast<float*>(d->coef32.p), geom->n_proj, s));
+    TileArgs a = make_args(vol, geom, 4, t, static_cast<unsigned char*>(d->adjoint.p),
+                           static_cast<float*>(d->coef32.p), const_cast<float*>(volume), out_scale, 0,
+                           FDK_F32);
+    HIP_TRY(launch_fp(a, t.strip, t.waves, s));
+    const int Wp = geom->width + kPadLo + kPadHi;
+    HIP_TRY(launch_unstage_add(static_cast<const float*>(d->adjoint.p), proj_out, geom->n_proj, geom->width,
+                               geom->height, Wp, a.proj_stride / 4, accumulate, s));
+    return end_call(*d, s);
+}
+
+fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width, int32_t height,
+                                int32_t dtype, void* dst, float* scale_out, void* stream)
+{
+    g_last_error.clear();
+    if (src == nullptr || dst == nullptr || scale_out == nullptr)
+        return fail(FDK_E_INVALID_ARG, "NULL pointer");
+    if (n_proj < 1 || width < 1 || height < 1) return fail(FDK_E_INVALID_ARG, "empty projection stack");
+    if (n_proj > 65535) return fail(FDK_E_INVALID_ARG, "n_proj=%d > 65535", n_proj);
+    if (dtype != FDK_F16 && dtype != FDK_BF16) return fail(FDK_E_UNSUPPORTED, "pack dtype must be F16 or BF16");
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState* d = nullptr;
+    fdk_status st = device_state(&d);
+    if (st != FDK_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(launch_pack(src, n_proj, width, height, dtype, dst, scale_out, s));
+    return FDK_OK;
+}
+
+fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int accumulate, void* stream)
+{
+    g_last_error.clear();
+    if (scans == nullptr) return fail(FDK_E_INVALID_ARG, "scans is NULL");
+    if (n_scans < 1 || n_scans > kMaxScans)
+        return fail(FDK_E_INVALID_ARG, "n_scans=%d outside [1, %d]", n_scans, kMaxScans);
+    int maxL = 0;
+    for (int i = 0; i < n_scans; ++i) {
+        fdk_status st = fdk_validate(&scans[i].vol, &scans[i].proj, 1);
+        if (st != FDK_OK) {
+            std::string m = g_last_error;
+            return fail(st, "scan %d: %s", i, m.c_str());
+        }
+        if (scans[i].volume == nullptr) return fail(FDK_E_INVALID_ARG, "scan %d: volume buffer is NULL", i);
+        maxL = std::max(maxL, scans[i].vol.L);
+    }
+    std::lock_guard<std::mutex> lock(g_mu);
+    load_env_tuning();
+    const TileShape t = pick_tile(maxL, FDK_F32);
+    DeviceState* d = nullptr;
+    fdk_status st = device_state(&d);
+    if (st != FDK_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    // cache key: every descriptor field, the matrices, the tile shape and accumulate
+    std::string key;
+    auto put = [&key](const void* x, size_t n) { key.append(static_cast<const char*>(x), n); };
+    put(&t, sizeof(t));
+    put(&accumulate, sizeof(int));
+    for (int i = 0; i < n_scans; ++i) {
+        const fdk_scan& sc = scans[i];
+        put(&sc.vol, sizeof(fdk_volume));
+        put(&sc.proj.n_proj, 4 * sizeof(int32_t));
+        put(&sc.proj.data, sizeof(void*));
+        put(&sc.proj.scale, sizeof(void*));
+        put(&sc.volume, sizeof(void*));
+        put(sc.proj.mats, (size_t)sc.proj.n_proj * 12 * sizeof(double));
+    }
+
+    // order: most expensive tiles (most projections) first
+    std::vector<int> order(n_scans);
+    for (int i = 0; i < n_scans; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return scans[a].proj.n_proj > scans[b].proj.n_proj; });
+    uint64_t stage_total = 0;
+    std::vector<uint64_t> stage_off(n_scans);
+    for (int j = 0; j < n_scans; ++j) {
+        const int i = order[j];
+        stage_off[j] = stage_total;
+        stage_total += staged_bytes(&scans[i].proj, esize_of(scans[i].proj.dtype));
+    }
+
+    if ((st = begin_call(*d, s)) != FDK_OK) return st;
+    if (d->batch_staged.n < stage_total) {
+        // growing the staging buffer invalidates every captured graph
+        HIP_TRY(hipDeviceSynchronize());
+        for (BatchEntry& b : d->batch_cache) {
+            if (b.exec) (void)hipGraphExecDestroy(b.exec);
+            release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
+            release(b.coef64); release(b.coef32); release(b.counter);
+        }
+        d->batch_cache.clear();
+        hipError_t e = ensure(d->batch_staged, stage_total);
+        if (e != hipSuccess) return fail(FDK_E_NOMEM, "batched staging workspace: %s", hipGetErrorString(e));
+    }
+
+    BatchEntry* hit = nullptr;
+    for (auto it = d->batch_cache.begin(); it != d->batch_cache.end(); ++it) {
+        if (it->key == key) {
+            d->batch_cache.splice(d->batch_cache.begin(), d->batch_cache, it);
+            hit = &d->batch_cache.front();
+            break;
+        }
+    }
+    if (hit == nullptr) {
+        if (d->batch_cache.size() >= kBatchCacheMax) {
+            HIP_TRY(hipDeviceSynchronize());
+            BatchEntry& b = d->batch_cache.back();
+            if (b.exec) (void)hipGraphExecDestroy(b.exec);
+            release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
+            release(b.coef64); release(b.coef32); release(b.counter);
+            d->batch_cache.pop_back();
+        }
+        // host tables
+        int total_proj = 0;
+        for (int i = 0; i < n_scans; ++i) total_proj += scans[i].proj.n_proj;
+        std::vector<double> coef64;
+        coef64.reserve((size_t)total_proj * 12);
+        std::vector<const float*> scale_ptrs;
+        scale_ptrs.reserve(total_proj);
+        std::vector<TileArgs> tiles(n_scans);
+        std::vector<StageArgs> stages(n_scans);
+        std::vector<int32_t> item_begin(n_scans + 1);
+        std::vector<float> out_scales(n_scans);
+        std::vector<int> proj_begin(n_scans);
+        int64_t rows = 0;
+        int64_t items = 0;
+        for (int j = 0; j < n_scans; ++j) {
+            const fdk_scan& sc = scans[order[j]];
+            Composed c = compose(&sc.vol, &sc.proj);
+            for (double x : c.coef)
+                if (!std::isfinite((float)x))
+                    return fail(FDK_E_INVALID_ARG, "scan %d: composed matrix exceeds FP32 range", order[j]);
+            proj_begin[j] = (int)(coef64.size() / 12);
+            coef64.insert(coef64.end(), c.coef.begin(), c.coef.end());
+            for (int k = 0; k < sc.proj.n_proj; ++k)
+                scale_ptrs.push_back(sc.proj.scale ? sc.proj.scale + k : nullptr);
+            out_scales[j] = c.out_scale;
+            const int es = esize_of(sc.proj.dtype);
+            stages[j] = make_stage(&sc.proj, es, static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j], rows);
+            rows += (int64_t)sc.proj.n_proj * stages[j].Hp;
+            item_begin[j] = (int32_t)items;
+            TileArgs probe = make_args(&sc.vol, &sc.proj, es, t, nullptr, nullptr, nullptr, 1.0f, 0, sc.proj.dtype);
+            items += (int64_t)probe.tiles_x * probe.tiles_y * probe.tiles_z;
+            if (items > 0x7fffffffLL) return fail(FDK_E_INVALID_ARG, "batch too large for one launch");
+        }
+        item_begin[n_scans] = (int32_t)items;
+        if (rows > 0x7fffffffLL) return fail(FDK_E_INVALID_ARG, "batch has too many projection rows");
+
+        BatchEntry b;
+        b.key = key;
+        hipError_t e = hipSuccess;
+        auto alloc = [&](DevBuf& buf, size_t n) { if (e == hipSuccess) e = ensure(buf, n); };
+        alloc(b.tiles, n_scans * sizeof(TileArgs));
+        alloc(b.item_begin, (n_scans + 1) * sizeof(int32_t));
+        alloc(b.stage, n_scans * sizeof(StageArgs));
+        alloc(b.scale_ptrs, (size_t)total_proj * sizeof(float*));
+        alloc(b.coef64, coef64.size() * sizeof(double));
+        alloc(b.coef32, (size_t)total_proj * 16 * sizeof(float));
+        alloc(b.counter, sizeof(unsigned));
+        if (e != hipSuccess) {
+            release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
+            release(b.coef64); release(b.coef32); release(b.counter);
+            return fail(FDK_E_NOMEM, "batched tables: %s", hipGetErrorString(e));
+        }
+        for (int j = 0; j < n_scans; ++j) {
+            const fdk_scan& sc = scans[order[j]];
+            tiles[j] = make_args(&sc.vol, &sc.proj, esize_of(sc.proj.dtype), t,
+                                 static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j],
+                                 static_cast<float*>(b.coef32.p) + (size_t)proj_begin[j] * 16, sc.volume,
+                                 out_scales[j], accumulate, sc.proj.dtype);
+        }
+        auto up = [&](DevBuf& buf, const void* src, size_t n) {
+            if (e == hipSuccess) e = hipMemcpyAsync(buf.p, src, n, hipMemcpyHostToDevice, s);
+        };
+        up(b.tiles, tiles.data(), tiles.size() * sizeof(TileArgs));
+        up(b.item_begin, item_begin.data(), item_begin.size() * sizeof(int32_t));
+        up(b.stage, stages.data(), stages.size() * sizeof(StageArgs));
+        up(b.scale_ptrs, scale_ptrs.data(), scale_ptrs.size() * sizeof(float*));
+        up(b.coef64, coef64.data(), coef64.size() * sizeof(double));
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess && d->capture_stream == nullptr)
+            e = hipStreamCreateWithFlags(&d->capture_stream, hipStreamNonBlocking);
+        // capture: stage every stack, fold the scales, reset the queue, run the persistent kernel
+        hipGraph_t graph = nullptr;
+        const int per_cu = batched_blocks_per_cu(t.strip, t.waves);
+        int grid = std::max(1, d->num_cus * std::max(1, per_cu));
+        if ((int64_t)grid > items) grid = (int)items;
+        if (e == hipSuccess) e = hipStreamBeginCapture(d->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e1 = launch_stage_batched(static_cast<const StageArgs*>(b.stage.p), n_scans, rows, d->capture_stream);
+            hipError_t e2 = launch_fold(static_cast<const double*>(b.coef64.p),
+                                        static_cast<const float* const*>(b.scale_ptrs.p),
+                                        static_cast<float*>(b.coef32.p), total_proj, d->capture_stream);
+            hipError_t e3 = launch_reset_counter(static_cast<unsigned*>(b.counter.p), d->capture_stream);
+            hipError_t e4 = launch_bp_batched(static_cast<const TileArgs*>(b.tiles.p),
+                                              static_cast<const int32_t*>(b.item_begin.p), n_scans,
+                                              static_cast<unsigned*>(b.counter.p), (int)items, grid,
+                                              t.strip, t.waves, d->capture_stream);
+            hipError_t ec = hipStreamEndCapture(d->capture_stream, &graph);
+            e = e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3 != hipSuccess ? e3 : e4 != hipSuccess ? e4 : ec;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b.exec, graph, nullptr, nullptr, 0);
+        if (graph != nullptr) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            if (b.exec) (void)hipGraphExecDestroy(b.exec);
+            release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
+            release(b.coef64); release(b.coef32); release(b.counter);
+            return fail(FDK_E_DEVICE, "batched graph build failed: %s", hipGetErrorString(e));
+        }
+        d->batch_cache.push_front(std::move(b));
+        hit = &d->batch_cache.front();
+    }
+    HIP_TRY(hipGraphLaunch(hit->exec, s));
+    return end_call(*d, s);
+}
+
+fdk_status fdk_set_tile(int32_t dtype, int32_t strip, int32_t waves)
+{
+    g_last_error.clear();
+    if (dtype < 0 || dtype > 2) return fail(FDK_E_UNSUPPORTED, "unknown dtype %d", dtype);
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (strip == 0 && waves == 0) {
+        g_tune.forced[dtype] = {0, 0};
+        return FDK_OK;
+    }
+    if (!supported_tile(strip, waves)) return fail(FDK_E_INVALID_ARG, "tile %dx%d not compiled", strip, waves);
+    g_tune.forced[dtype] = {strip, waves};
+    return FDK_OK;
+}
+
+fdk_status fdk_get_tile(const fdk_volume* vol, int32_t dtype, int32_t* strip, int32_t* waves)
+{
+    g_last_error.clear();
+    fdk_status st = check_volume(vol);
+    if (st != FDK_OK) return st;
+    if (dtype < 0 || dtype > 2) return fail(FDK_E_UNSUPPORTED, "unknown dtype %d", dtype);
+    if (strip == nullptr || waves == nullptr) return fail(FDK_E_INVALID_ARG, "NULL output");
+    std::lock_guard<std::mutex> lock(g_mu);
+    load_env_tuning();
+    const TileShape t = pick_tile(vol->L, dtype);
+    *strip = t.strip;
+    *waves = t.waves;
+    return FDK_OK;
+}
+
+fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip, int32_t waves)
+{
+    g_last_error.clear();
+    if (dtype < 0 || dtype > 2) return fail(FDK_E_UNSUPPORTED, "unknown dtype %d", dtype);
+    if (size_class < 0 || size_class > 15) return fail(FDK_E_INVALID_ARG, "size class %d", size_class);
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (strip == 0 && waves == 0) {
+        g_tune.table.erase({dtype, size_class});
+        return FDK_OK;
+    }
+    if (!supported_tile(strip, waves)) return fail(FDK_E_INVALID_ARG, "tile %dx%d not compiled", strip, waves);
+    g_tune.table[{dtype, size_class}] = {strip, waves};
+    return FDK_OK;
+}
+
+int32_t fdk_load_tuning(const char* path)
+{
+    g_last_error.clear();
+    if (path == nullptr) return fail(FDK_E_INVALID_ARG, "path is NULL");
+    FILE* f = std::fopen(path, "r");
+    if (f == nullptr) return fail(FDK_E_INVALID_ARG, "cannot open %s", path);
+    char line[256];
+    int n = 0;
+    bool header = false;
+    std::vector<std::pair<std::pair<int, int>, TileShape>> entries;
+    while (std::fgets(line, sizeof(line), f)) {
+        char* hash = std::strchr(line, '#');
+        if (hash) *hash = 0;
+        char tag[64], arch[64];
+        int ver = 0;
+        if (!header) {
+            if (std::sscanf(line, "%63s %d %63s", tag, &ver, arch) == 3) {
+                if (std::strcmp(tag, "fdk-tuning") != 0 || ver != FDK_ABI_VERSION || std::strcmp(arch, "gfx950") != 0) {
+                    std::fclose(f);
+                    return fail(FDK_E_INVALID_ARG, "%s: tuning file is for another version or arch", path);
+                }
+                header = true;
+            }
+            continue;
+        }
+        int dt, cls, s, w;
+        if (std::sscanf(line, "%d %d %d %d", &dt, &cls, &s, &w) == 4) {
+            if (dt < 0 || dt > 2 || cls < 0 || cls > 15 || !supported_tile(s, w)) {
+                std::fclose(f);
+                return fail(FDK_E_INVALID_ARG, "%s: bad entry '%d %d %d %d'", path, dt, cls, s, w);
+            }
+            entries.push_back({{dt, cls}, {s, w}});
+            ++n;
+        }
+    }
+    std::fclose(f);
+    if (!header) return fail(FDK_E_INVALID_ARG, "%s: missing 'fdk-tuning' header", path);
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto& e : entries) g_tune.table[e.first] = e.second;
+    return n;
+}
+
+fdk_status fdk_release_workspace(void)
+{
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lock(g_mu);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto it = g_dev.find(dev);
+    if (it == g_dev.end()) return FDK_OK;
+    DeviceState& d = it->second;
+    HIP_TRY(hipDeviceSynchronize());
+    release(d.staged);
+    release(d.coef32);
+    release(d.adjoint);
+    for (CoefEntry& c : d.coef_cache) release(c.buf);
+    d.coef_cache.clear();
+    for (BatchEntry& b : d.batch_cache) {
+        if (b.exec) (void)hipGraphExecDestroy(b.exec);
+        release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
+        release(b.coef64); release(b.coef32); release(b.counter);
+    }
+    d.batch_cache.clear();
+    release(d.batch_staged);
+    d.have_last = false;
+    return FDK_OK;
+}
+
+}  // extern "C"

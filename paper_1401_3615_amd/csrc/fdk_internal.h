@@ -1,0 +1,76 @@
+// Internal interface between the host layer (fdk_api.cpp) and the gfx950
+// kernels (fdk_kernels.hip).  Not installed; the public ABI is include/fdk.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdk {
+
+// Zero border around every staged projection: two columns/rows before the
+// detector and three after.  A detector coordinate clamped to [-2, W+1] then
+// always addresses a 2x2 tap block inside the staged image, and every tap that
+// lies off the detector reads a stored zero (the paper's zero-padding).
+constexpr int kPadLo = 2;
+constexpr int kPadHi = 3;
+constexpr int kWave = 64;
+
+// Per-scan arguments of the backprojection / forward-projection tile body.
+// Coordinates inside the kernels are centred: the voxel index is offset by
+// `ctr` on every axis and the detector column/row by (cu, cv) = (W/2, H/2),
+// both integers, so floor() and the fraction are unchanged while the FP32
+// magnitudes of u, v, x, y, z halve.
+struct TileArgs {
+    const unsigned char* proj;   // staged padded projections (or adjoint accumulation buffer)
+    const float* coef;           // n_proj x 16 floats: rows u, v, w of the composed matrix
+    float* vol;                  // volume buffer (planes z_begin .. z_begin + z_count)
+    uint64_t proj_stride;        // bytes between consecutive staged projections
+    int32_t n_proj;
+    int32_t L;
+    int32_t z_begin;
+    int32_t z_count;
+    int32_t ctr;                 // voxel index centre offset
+    uint32_t row_bytes;          // staged row pitch in bytes
+    uint32_t centre_bytes;       // byte offset of detector pixel (cu, cv) in a staged image
+    uint32_t proj_bytes;         // bytes of one staged image (buffer range limit)
+    float lo_x, hi_x, lo_y, hi_y;  // clamp range of centred coordinates ([-2, W+1] - cu ...)
+    float out_scale;             // power-of-two renormalisation of the 1/w^2 weight
+    int32_t accumulate;
+    int32_t tiles_x, tiles_y, tiles_z;
+    int32_t dtype;               // fdk_dtype of the staged images
+    int32_t pad_;
+};
+
+// One projection stack to stage into the padded layout.
+struct StageArgs {
+    const void* src;             // [n][H][W] elements of esize bytes
+    unsigned char* dst;          // staged images, proj_stride apart
+    uint64_t proj_stride;        // bytes
+    int32_t n, W, H, Wp, Hp;
+    int32_t esize;               // 2 or 4
+    int64_t row_begin;           // first global row index of this stack (batched staging)
+};
+
+// Launch wrappers (fdk_kernels.hip).  All return the launch's hipError_t.
+hipError_t launch_stage(const StageArgs& a, hipStream_t s);
+hipError_t launch_stage_batched(const StageArgs* dev_args, int n_stacks, int64_t total_rows,
+                                hipStream_t s);
+hipError_t launch_fold(const double* coef64, const float* const* scale_ptrs, float* coef32,
+                       int n_total, hipStream_t s);
+hipError_t launch_fold_single(const double* coef64, const float* scale, float* coef32, int n,
+                              hipStream_t s);
+hipError_t launch_bp(const TileArgs& a, int strip, int waves, hipStream_t s);
+hipError_t launch_fp(const TileArgs& a, int strip, int waves, hipStream_t s);
+hipError_t launch_bp_batched(const TileArgs* dev_scans, const int32_t* dev_item_begin, int n_scans,
+                             unsigned* dev_counter, int total_items, int grid, int strip, int waves,
+                             hipStream_t s);
+hipError_t launch_reset_counter(unsigned* counter, hipStream_t s);
+hipError_t launch_fill(float* p, uint64_t n, float value, hipStream_t s);
+hipError_t launch_unstage_add(const float* padded, float* out, int n, int W, int H, int Wp,
+                              uint64_t stride_elems, int accumulate, hipStream_t s);
+hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* dst, float* scale,
+                       hipStream_t s);
+int supported_tile(int strip, int waves);
+int batched_blocks_per_cu(int strip, int waves);
+
+}  // namespace fdk

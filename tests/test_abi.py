@@ -1,0 +1,179 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/fdk.h, and rejects bad arguments on
+the host before touching the device."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from tests._common import ROOT, ensure_built
+
+
+@pytest.fixture(scope="module")
+def fdk():
+    ensure_built()
+    import paper_1401_3615_amd as m
+    m.load()
+    return m
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "fdk.h")).read()
+    return sorted(set(re.findall(r"\b(fdk_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(fdk):
+    lib = fdk.load()
+    names = declared_symbols()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), n
+    assert fdk.abi_version() == 1
+
+
+def test_status_strings(fdk):
+    lib = fdk.load()
+    for code, name in [(0, b"FDK_OK"), (-1, b"FDK_E_INVALID_ARG"), (-2, b"FDK_E_GEOMETRY"),
+                       (-3, b"FDK_E_UNSUPPORTED"), (-4, b"FDK_E_NOMEM"), (-5, b"FDK_E_DEVICE")]:
+        assert lib.fdk_status_string(code) == name
+
+
+def _case(L=16, N=4, W=32, H=24):
+    mats = S.tiny_cone_matrices(N, W, H, L, 1.0, 0)
+    return mats, W, H
+
+
+def test_validate_accepts_good_geometry(fdk):
+    mats, W, H = _case()
+    fdk.validate(fdk.Geometry(mats, W, H), fdk.Volume(16, 1.0))
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda v, g: setattr(v, "L", 0), -1),
+    (lambda v, g: setattr(v, "voxel_mm", 0.0), -1),
+    (lambda v, g: setattr(v, "voxel_mm", float("nan")), -1),
+    (lambda v, g: setattr(v, "z_begin", 16), -1),
+    (lambda v, g: setattr(v, "z_count", 17), -1),
+    (lambda v, g: setattr(v, "origin_mm", (0.0, float("inf"), 0.0)), -1),
+    (lambda v, g: setattr(g, "width", 0), -1),
+    (lambda v, g: setattr(g, "height", 1 << 23), -1),
+])
+def test_validate_rejects(fdk, mutate, status):
+    mats, W, H = _case()
+    g = fdk.Geometry(mats, W, H)
+    v = fdk.Volume(16, 1.0, z_begin=0, z_count=16)
+    mutate(v, g)
+    with pytest.raises(fdk.FdkError) as ei:
+        fdk.validate(g, v)
+    assert ei.value.status == status
+
+
+def test_validate_rejects_nonfinite_matrix(fdk):
+    mats, W, H = _case()
+    mats[2, 1, 3] = np.nan
+    with pytest.raises(fdk.FdkError) as ei:
+        fdk.validate(fdk.Geometry(mats, W, H), fdk.Volume(16, 1.0))
+    assert ei.value.status == -1
+    assert "matrix 2" in str(ei.value)
+
+
+def test_geometry_error_names_projection_and_corner(fdk):
+    mats, W, H = _case()
+    mats[3] = -mats[3]
+    with pytest.raises(fdk.FdkError) as ei:
+        fdk.validate(fdk.Geometry(mats, W, H), fdk.Volume(16, 1.0))
+    assert ei.value.status == -2
+    assert "projection 3" in str(ei.value)
+
+
+def test_geometry_checked_on_processed_slab_only(fdk):
+    """w <= 0 only in planes outside the slab is accepted for that slab."""
+    L = 16
+    mats = np.zeros((1, 3, 4))
+    mats[0, 0, 0] = mats[0, 1, 1] = 1.0
+    mats[0, 2, 2] = 1.0  # w = Z: positive only for z > 0 in world terms
+    vol_all = fdk.Volume(L, 1.0, origin_mm=(0.0, 0.0, -7.5))
+    with pytest.raises(fdk.FdkError):
+        fdk.validate(fdk.Geometry(mats, 8, 8), vol_all)
+    fdk.validate(fdk.Geometry(mats, 8, 8), vol_all.slab(8, 8))
+
+
+def test_unsupported_dtype(fdk):
+    mats, W, H = _case()
+    lib = fdk.load()
+    v = fdk.Volume(16, 1.0).c()
+    p = fdk.Geometry(mats, W, H).c(data=1, dtype=7)
+    assert lib.fdk_validate(ctypes.byref(v), ctypes.byref(p), 1) == -3
+
+
+def test_invalid_calls_do_not_touch_the_device(fdk):
+    """Argument errors are reported before any HIP call (this host has no GPU)."""
+    lib = fdk.load()
+    mats, W, H = _case()
+    v = fdk.Volume(16, 1.0).c()
+    p = fdk.Geometry(mats, W, H).c(data=None)
+    assert lib.fdk_backproject(ctypes.byref(v), ctypes.byref(p), 1, 0, None) == -1
+    assert b"data is NULL" in lib.fdk_last_error()
+    p = fdk.Geometry(mats, W, H).c(data=1)
+    assert lib.fdk_backproject(ctypes.byref(v), ctypes.byref(p), None, 0, None) == -1
+    assert lib.fdk_forwardproject(ctypes.byref(v), None, ctypes.byref(p), 1, 0, None) == -1
+    assert lib.fdk_backproject(None, ctypes.byref(p), 1, 0, None) == -1
+    assert lib.fdk_backproject_batched(None, 1, 0, None) == -1
+    assert lib.fdk_pack_projections(1, 4, 8, 8, 0, 1, 1, None) == -3
+    assert lib.fdk_pack_projections(None, 4, 8, 8, 1, 1, 1, None) == -1
+
+
+def test_batched_reports_failing_scan(fdk):
+    lib = fdk.load()
+    mats, W, H = _case()
+    bad = mats.copy()
+    bad[0] = -bad[0]
+    arr = (fdk._Scan * 3)()
+    keep = []
+    for i, m in enumerate([mats, mats, bad]):
+        g = fdk.Geometry(m, W, H)
+        keep.append(g)
+        arr[i].vol = fdk.Volume(16, 1.0).c()
+        arr[i].proj = g.c(data=1)
+        arr[i].volume = 1
+    assert lib.fdk_backproject_batched(arr, 3, 0, None) == -2
+    assert b"scan 2" in lib.fdk_last_error()
+
+
+def test_tiles_and_tuning_file(fdk, tmp_path):
+    vol = fdk.Volume(512, 0.5)
+    fdk.set_tile(fdk.F16, 4, 1)
+    assert fdk.get_tile(vol, fdk.F16) == (4, 1)
+    fdk.set_tile(fdk.F16, 0, 0)
+    with pytest.raises(fdk.FdkError):
+        fdk.set_tile(fdk.F32, 3, 1)
+    f = tmp_path / "tune.txt"
+    f.write_text("fdk-tuning 1 gfx950\n# dtype class strip waves\n0 9 8 1\n1 9 2 2\n")
+    assert fdk.load_tuning(str(f)) == 2
+    assert fdk.get_tile(vol, fdk.F32) == (8, 1)
+    assert fdk.get_tile(vol, fdk.F16) == (2, 2)
+    stale = tmp_path / "stale.txt"
+    stale.write_text("fdk-tuning 0 gfx942\n0 9 4 4\n")
+    with pytest.raises(fdk.FdkError):
+        fdk.load_tuning(str(stale))
+    assert fdk.get_tile(vol, fdk.F32) == (8, 1)   # stale file ignored
+    bad = tmp_path / "bad.txt"
+    bad.write_text("fdk-tuning 1 gfx950\n0 9 5 1\n")
+    with pytest.raises(fdk.FdkError):
+        fdk.load_tuning(str(bad))
+    fdk.set_tuning_entry(0, 9, 16, 2)
+    assert fdk.get_tile(vol, fdk.F32) == (16, 2)
+    for dt in (0, 1):
+        fdk.set_tuning_entry(dt, 9, 0, 0)   # restore the built-in choice
+    assert fdk.get_tile(vol, fdk.F32) == fdk.get_tile(vol, fdk.F32)
+
+
+def test_header_struct_layout(fdk):
+    """The ctypes mirror has the sizes the C structs have."""
+    assert ctypes.sizeof(fdk._Volume) == 48
+    assert ctypes.sizeof(fdk._Proj) == 40
+    assert ctypes.sizeof(fdk._Scan) == 96
