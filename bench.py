@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Throughput of voxel-driven FDK backprojection on one MI355X.
+
+Headline workload: a 512^3 volume (0.5 mm voxels) backprojected from 496
+filtered 1248x960 projections of a seeded ellipsoid phantom on a 200-degree
+C-arm short scan (the paper's RabbitCT shapes).  One step is one
+fdk_backproject call on FP32 projections (matrix conditioning from the cached
+table, zero-padded staging, coefficient fold, backprojection kernel); `value`
+is L^3 * N / step time in GUp/s with the projections resident in HBM.
+
+The same JSON line carries the other forms measured on the same GPU: FP16 and
+BF16 projection storage, the adjoint (forward projector), the batched
+persistent launch of 16 uneven scans against one launch per scan, and the
+1024^3 volume processed as z-slabs; plus the roofline of the backprojection
+kernel and the FP64 oracle timed on the host cores as the CPU baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--legs ...]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_UPDATE = 23          # algorithmic FP operations of one voxel update
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+PEAK_FP32_NONPACKED = 78.6    # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, without packed FP32
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "bp_f32_512x496_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1401_3615_amd", "csrc", "fdk_kernels.hip")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def time_steps(fn, steps: int, warmup: int, stream):
+    """Untimed warm-up, then `steps` calls bracketed by synchronisation and
+    HIP events on the launch stream; returns ms per step."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--legs", default="fp16,bf16,adjoint,batched,slab1024",
+                    help="comma list of extra legs (fp16,bf16,adjoint,batched,slab1024) or 'none'")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run only warm-up and timed FP32 steps (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(z-slab sharding is a design note only); run with --gpus 1", file=sys.stderr)
+        return 2
+    legs = set() if args.legs == "none" else set(args.legs.split(","))
+
+    import numpy as np
+    import torch
+
+    import paper_1401_3615_amd as fdk
+    from paper_1401_3615_amd import _build
+    import synthetic as S
+
+    if not os.path.exists(_build.LIB):
+        log("library not built; building")
+        _build.build_library(force=True)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    # ---------------------------------------------------------------- workload
+    L, voxel, N = 512, 0.5, 496
+    carm = S.CArm(N)
+    t0 = time.time()
+    mats, q = S.filtered_projections(carm, seed=0, device=dev)
+    q = q.contiguous()
+    torch.cuda.synchronize()
+    log(f"phantom projections {tuple(q.shape)} generated on the GPU in {time.time() - t0:.1f} s")
+    geom = fdk.Geometry(mats, carm.width, carm.height)
+    vol = fdk.Volume(L, voxel)
+    out = torch.empty((L, L, L), dtype=torch.float32, device=dev)
+    updates = L ** 3 * N
+
+    # ---------------------------------------------------------------- FP32 headline
+    bp32 = lambda: fdk.backproject(q, geom, vol, out=out)
+    fdk.profile_enable(False)
+    for _ in range(args.warmup):
+        bp32()
+    torch.cuda.synchronize()
+    fdk.profile_enable(True)
+    ms = time_steps(bp32, args.steps, 0, stream)
+    n_bp, bp_ms_total = fdk.profile_read("bp")
+    n_st, st_ms_total = fdk.profile_read("stage")
+    fdk.profile_enable(False)
+    bp_kernel_ms = bp_ms_total / max(n_bp, 1)
+    stage_ms = st_ms_total / max(n_st, 1)
+    value = updates / (ms * 1e-3) / 1e9
+    log(f"fp32: {ms:.2f} ms/step, {value:.1f} GUp/s (bp kernel {bp_kernel_ms:.2f} ms, staging {stage_ms:.2f} ms)")
+    if args.profile_only:
+        print(json.dumps({"metric": "fp32_gups", "value": value, "ms_per_step": ms}), flush=True)
+        return 0
+    vol32 = out.clone()
+
+    extra = {}
+    # ---------------------------------------------------------------- FP16 / BF16 storage
+    packed = {}
+    for name, tdt in (("fp16", torch.float16), ("bf16", torch.bfloat16)):
+        if name not in legs:
+            continue
+        pk_ms = time_steps(lambda: fdk.pack_projections(q, tdt), 1, 1, stream)
+        qp, sc = fdk.pack_projections(q, tdt)
+        fn = lambda qp=qp, sc=sc: fdk.backproject(qp, geom, vol, out=out, scale=sc)
+        m = time_steps(fn, args.steps, args.warmup, stream)
+        packed[name] = out.clone()
+        extra[f"{name}_gups"] = updates / (m * 1e-3) / 1e9
+        extra[f"{name}_ms_per_step"] = m
+        extra[f"{name}_pack_ms"] = pk_ms
+        log(f"{name}: {m:.2f} ms/step, {extra[f'{name}_gups']:.1f} GUp/s (pack {pk_ms:.2f} ms, not in step)")
+        del qp, sc
+
+    # ---------------------------------------------------------------- adjoint
+    if "adjoint" in legs:
+        pout = torch.empty_like(q)
+        fn = lambda: fdk.forwardproject(vol32, geom, vol, out=pout)
+        m = time_steps(fn, max(1, min(args.steps, 3)), 1, stream)
+        extra["adjoint_gups"] = updates / (m * 1e-3) / 1e9
+        extra["adjoint_ms_per_step"] = m
+        log(f"adjoint 512^3x496: {m:.2f} ms/step, {extra['adjoint_gups']:.1f} GUp/s")
+        del pout
+
+    # ---------------------------------------------------------------- 1024^3 in z-slabs
+    if "slab1024" in legs:
+        L2, vox2 = 1024, 0.25
+        big = torch.empty((L2, L2, L2), dtype=torch.float32, device=dev)
+        slabs = [(z, 256) for z in range(0, L2, 256)]
+        base = fdk.Volume(L2, vox2)
+
+        def slab_run():
+            for z0, nz in slabs:
+                fdk.backproject(q, geom, base.slab(z0, nz), out=big[z0:z0 + nz])
+        m = time_steps(slab_run, max(1, min(args.steps, 3)), 1, stream)
+        extra["slab1024_gups"] = L2 ** 3 * N / (m * 1e-3) / 1e9
+        extra["slab1024_ms_per_step"] = m
+        log(f"1024^3 x 496 in {len(slabs)} z-slabs: {m:.1f} ms, {extra['slab1024_gups']:.1f} GUp/s")
+        del big
+
+    # ---------------------------------------------------------------- batched
+    if "batched" in legs:
+        specs = S.batched_scan_specs(16, seed=100)
+        scans = []
+        gen = torch.Generator(device=dev)
+        for sp in specs:
+            gen.manual_seed(sp.seed)
+            c = sp.carm()
+            pr = torch.randn((sp.n_proj, sp.height, sp.width), device=dev, generator=gen)
+            scans.append(fdk.Scan(pr, fdk.Geometry(S.carm_matrices(c), sp.width, sp.height),
+                                  fdk.Volume(sp.L, sp.voxel_mm),
+                                  torch.empty((sp.L, sp.L, sp.L), device=dev)))
+        total = sum(sp.L ** 3 * sp.n_proj for sp in specs)
+        mb = time_steps(lambda: fdk.backproject_batched(scans), max(1, args.steps // 2), 1, stream)
+
+        def one_at_a_time():
+            for s in scans:
+                fdk.backproject(s.proj, s.geom, s.vol, out=s.out)
+        mo = time_steps(one_at_a_time, max(1, args.steps // 2), 1, stream)
+        extra["batched_gups"] = total / (mb * 1e-3) / 1e9
+        extra["batched_one_at_a_time_gups"] = total / (mo * 1e-3) / 1e9
+        extra["batched_ms_per_step"] = mb
+        log(f"batched 16 scans: {mb:.1f} ms ({extra['batched_gups']:.1f} GUp/s) vs one at a time "
+            f"{mo:.1f} ms ({extra['batched_one_at_a_time_gups']:.1f} GUp/s)")
+        del scans
+
+    # ---------------------------------------------------------------- roofline
+    achieved = FLOP_PER_UPDATE * updates / (bp_kernel_ms * 1e-3) / 1e12
+    traffic = None
+    if os.path.exists(COUNTERS_FILE):
+        with open(COUNTERS_FILE) as f:
+            cnt = json.load(f)
+        if cnt.get("kernel_source_sha256") == kernel_hash():
+            traffic = cnt["hbm_bytes_per_launch"]
+    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "kernel": "bp_kernel<float>", "kernel_ms": round(bp_kernel_ms, 3),
+                "flop_per_update": FLOP_PER_UPDATE,
+                "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED, 4)}
+
+    # ---------------------------------------------------------------- CPU oracle baseline + accuracy
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        q64 = q.cpu().numpy().astype(np.float64)
+        slabs_z = [(120, 16), (376, 16)]
+        t0 = time.time()
+        refs = [oracle.backproject(L, voxel, mats, q64, z_range=zr) for zr in slabs_z]
+        dt = time.time() - t0
+        nup = sum(nz for _, nz in slabs_z) * L * L * N
+        cpu = {"value": round(nup / dt / 1e9, 4), "unit": "GUp/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"planes z=120..135 and 376..391 of 512^3 x 496 ({nup:.3g} updates, {dt:.1f} s)"}
+        ref = np.concatenate(refs)
+        zsel = np.concatenate([np.arange(z, z + nz) for z, nz in slabs_z])
+        acc = {}
+        for name, v in [("fp32", vol32)] + list(packed.items()):
+            got = v[torch.as_tensor(zsel, device=dev)].cpu().numpy()
+            acc[name] = {"rel_l2": float(f"{oracle.rel_l2(got, ref):.3e}"),
+                         "psnr_db": round(oracle.psnr(got, ref), 2)}
+        extra["accuracy_vs_oracle"] = acc
+        log(f"oracle {cpu['value']} GUp/s on {cpu['cores']} threads; accuracy {acc}")
+        del q64
+
+    line = {
+        "metric": "GUp/s at 512^3 vol x 496 proj: FP32 vs FP16-proj; fwd+adjoint GUp/s",
+        "value": round(value, 2),
+        "unit": "GUp/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "fdk_backproject 512^3 @0.5mm <- 496 x 1248x960 fp32, 200deg C-arm, "
+                               "10-ellipsoid phantom seed 0",
+                   "L": L, "n_proj": N, "detector": [carm.height, carm.width]},
+        "supported_update_fraction_note": "value counts L^3*N nominal updates",
+        "staging_ms": round(stage_ms, 3),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    line.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in extra.items()})
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

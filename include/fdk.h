@@ -162,7 +162,7 @@ fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width,
 
 /* Tile shape of the backprojection kernel: each lane of a 64-wide wavefront
  * owns one x column and a strip of `strip` voxels along y; a workgroup stacks
- * `waves` wavefronts along z.  strip in {2, 4, 8, 16}, waves in {1, 2, 4}.
+ * `waves` wavefronts along z.  strip in {2, 4, 8, 16, 32}, waves in {1, 2, 4}.
  * fdk_set_tile pins the shape for a dtype (0, 0 restores automatic choice from
  * the tuning table); fdk_get_tile reports the shape a call with this grid and
  * dtype would use. */
@@ -185,6 +185,15 @@ fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip
  * performs, without touching the GPU. */
 fdk_status fdk_validate(const fdk_volume* vol, const fdk_projections* proj,
                         int need_data);
+
+/* Kernel timing for measurement: while enabled, every kernel launch of the
+ * library is bracketed by HIP events on its stream.  fdk_profile_read waits for
+ * the recorded events and returns, for one kernel kind ("stage", "fold", "bp",
+ * "fp", "fill", "unstage", "pack", "batched"), the number of launches and their
+ * summed duration in milliseconds since the last fdk_profile_enable call
+ * (which clears the records). */
+fdk_status fdk_profile_enable(int enable);
+fdk_status fdk_profile_read(const char* kernel, int64_t* launches, double* total_ms);
 
 /* Releases the calling thread's current-device workspace and cached graphs
  * (waits for the device first). */

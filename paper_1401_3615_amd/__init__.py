@@ -24,7 +24,7 @@ __all__ = [
     "FdkError", "Volume", "Geometry", "F32", "F16", "BF16", "load", "backproject",
     "forwardproject", "backproject_batched", "pack_projections", "set_tile", "get_tile",
     "load_tuning", "set_tuning_entry", "validate", "release_workspace", "abi_version",
-    "BackProject", "ForwardProject", "Scan",
+    "BackProject", "ForwardProject", "Scan", "profile_enable", "profile_read",
 ]
 
 F32, F16, BF16 = 0, 1, 2
@@ -81,6 +81,9 @@ def load():
         "fdk_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "fdk_last_error": ([], ctypes.c_char_p),
         "fdk_abi_version": ([], i32),
+        "fdk_profile_enable": ([ctypes.c_int], ctypes.c_int),
+        "fdk_profile_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -296,6 +299,18 @@ def validate(geom: Geometry, vol: Volume, need_data: bool = False, dtype: int = 
 
 def release_workspace() -> None:
     _check(load().fdk_release_workspace())
+
+
+def profile_enable(enable: bool = True) -> None:
+    """Start (and clear) or stop per-launch HIP-event timing inside the library."""
+    _check(load().fdk_profile_enable(int(bool(enable))))
+
+
+def profile_read(kernel: str) -> tuple[int, float]:
+    """(launches, total milliseconds) of one kernel kind since profile_enable."""
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(load().fdk_profile_read(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 def abi_version() -> int:

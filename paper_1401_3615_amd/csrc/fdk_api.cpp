@@ -159,6 +159,56 @@ Composed compose(const fdk_volume* v, const fdk_projections* p)
     return c;
 }
 
+// ------------------------------------------------------------------ kernel timing
+// When enabled, every launch is bracketed by a pair of HIP events on the
+// launch's stream; fdk_profile_read sums the elapsed times per kernel kind.
+struct ProfRecord {
+    const char* kind;
+    hipEvent_t start, end;
+};
+
+struct Profiler {
+    bool on = false;
+    std::vector<ProfRecord> records;
+    std::vector<hipEvent_t> pool;
+};
+
+Profiler g_prof;
+constexpr size_t kProfMax = 1 << 16;
+
+hipEvent_t prof_event()
+{
+    if (!g_prof.pool.empty()) {
+        hipEvent_t e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// RAII bracket: records the start event now and the end event at scope exit.
+struct ProfScope {
+    const char* kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(const char* k, hipStream_t st) : kind(k), s(st)
+    {
+        if (!g_prof.on || g_prof.records.size() >= kProfMax) return;
+        a = prof_event();
+        b = prof_event();
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    ~ProfScope()
+    {
+        if (a && b) {
+            (void)hipEventRecord(b, s);
+            g_prof.records.push_back({kind, a, b});
+        }
+    }
+};
+
 // ------------------------------------------------------------------ tiles
 struct TileShape { int strip, waves; };
 
@@ -175,11 +225,17 @@ int size_class(int L)
     return c;
 }
 
+// Built-in choice when no tuning entry applies: the longest strip (fewer
+// per-projection set-ups per voxel) that still gives ~4 workgroups per CU on
+// a 256-CU device.
 TileShape default_tile(int L)
 {
-    if (L >= 256) return {16, 2};
-    if (L >= 96) return {8, 2};
-    return {4, 2};
+    const int64_t want = 1024;
+    for (int strip : {32, 16, 8, 4}) {
+        const int64_t tiles = (int64_t)((L + 63) / 64) * ((L + strip - 1) / strip) * ((L + 1) / 2);
+        if (tiles >= want) return {strip, 2};
+    }
+    return {2, 2};
 }
 
 // ------------------------------------------------------------------ device state
@@ -223,7 +279,7 @@ struct CoefEntry {
 struct BatchEntry {
     std::string key;
     hipGraphExec_t exec = nullptr;
-    DevBuf tiles, item_begin, stage, scale_ptrs, coef64, coef32, counter;
+    DevBuf tiles, item_begin, stage, scale_ptrs, coef64, coef_dev, counter;
 };
 
 struct DeviceState {
@@ -231,7 +287,7 @@ struct DeviceState {
     bool arch_ok = false;
     int num_cus = 0;
     std::string arch;
-    DevBuf staged, coef32, adjoint;
+    DevBuf staged, coef_dev, adjoint;
     std::list<CoefEntry> coef_cache;   // most recent first
     hipStream_t last_stream = nullptr;
     bool have_last = false;
@@ -350,7 +406,7 @@ TileShape pick_tile(int L, int dtype)
 void load_env_tuning();
 
 TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, TileShape t,
-                   const unsigned char* staged, const float* coef32, float* vol, float out_scale,
+                   const unsigned char* staged, const double* coef_dev, float* vol, float out_scale,
                    int accumulate, int dtype)
 {
     TileArgs a;
@@ -359,7 +415,7 @@ TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, Til
     const int Wp = W + kPadLo + kPadHi, Hp = H + kPadLo + kPadHi;
     const int cu = W / 2, cv = H / 2;
     a.proj = staged;
-    a.coef = coef32;
+    a.coef = coef_dev;
     a.vol = vol;
     const uint64_t img = (uint64_t)Wp * Hp * esize;
     a.proj_stride = (img + 255) & ~uint64_t(255);
@@ -473,18 +529,27 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     if ((st = begin_call(*d, s)) != FDK_OK) return st;
     hipError_t e = ensure(d->staged, staged_bytes(proj, es));
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "staging workspace: %s", hipGetErrorString(e));
-    e = ensure(d->coef32, (size_t)proj->n_proj * 16 * sizeof(float));
+    e = ensure(d->coef_dev, (size_t)proj->n_proj * 16 * sizeof(double));
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "coefficient workspace: %s", hipGetErrorString(e));
     const double* coef64 = nullptr;
     float out_scale = 1.0f;
     if ((st = coef_table(*d, vol, proj, s, &coef64, &out_scale)) != FDK_OK) return st;
 
     StageArgs sa = make_stage(proj, es, static_cast<unsigned char*>(d->staged.p), 0);
-    HIP_TRY(launch_stage(sa, s));
-    HIP_TRY(launch_fold_single(coef64, proj->scale, static_cast<float*>(d->coef32.p), proj->n_proj, s));
+    {
+        ProfScope ps("stage", s);
+        HIP_TRY(launch_stage(sa, s));
+    }
+    {
+        ProfScope ps("fold", s);
+        HIP_TRY(launch_fold_single(coef64, proj->scale, static_cast<double*>(d->coef_dev.p), proj->n_proj, s));
+    }
     TileArgs a = make_args(vol, proj, es, t, static_cast<unsigned char*>(d->staged.p),
-                           static_cast<float*>(d->coef32.p), volume, out_scale, accumulate, proj->dtype);
-    HIP_TRY(launch_bp(a, t.strip, t.waves, s));
+                           static_cast<double*>(d->coef_dev.p), volume, out_scale, accumulate, proj->dtype);
+    {
+        ProfScope ps("bp", s);
+        HIP_TRY(launch_bp(a, t.strip, t.waves, s));
+    }
     return end_call(*d, s);
 }
 
@@ -508,21 +573,33 @@ fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const 
     const uint64_t bytes = staged_bytes(geom, 4);
     hipError_t e = ensure(d->adjoint, bytes);
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "adjoint workspace: %s", hipGetErrorString(e));
-    e = ensure(d->coef32, (size_t)geom->n_proj * 16 * sizeof(float));
+    e = ensure(d->coef_dev, (size_t)geom->n_proj * 16 * sizeof(double));
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "coefficient workspace: %s", hipGetErrorString(e));
     const double* coef64 = nullptr;
     float out_scale = 1.0f;
     if ((st = coef_table(*d, vol, geom, s, &coef64, &out_scale)) != FDK_OK) return st;
 
-    HIP_TRY(launch_fill(static_cast<float*>(d->adjoint.p), bytes / 4, 0.0f, s));
-    HIP_TRY(launch_fold_single(coef64, nullptr, static_cast<float*>(d->coef32.p), geom->n_proj, s));
+    {
+        ProfScope ps("fill", s);
+        HIP_TRY(launch_fill(static_cast<float*>(d->adjoint.p), bytes / 4, 0.0f, s));
+    }
+    {
+        ProfScope ps("fold", s);
+        HIP_TRY(launch_fold_single(coef64, nullptr, static_cast<double*>(d->coef_dev.p), geom->n_proj, s));
+    }
     TileArgs a = make_args(vol, geom, 4, t, static_cast<unsigned char*>(d->adjoint.p),
-                           static_cast<float*>(d->coef32.p), const_cast<float*>(volume), out_scale, 0,
+                           static_cast<double*>(d->coef_dev.p), const_cast<float*>(volume), out_scale, 0,
                            FDK_F32);
-    HIP_TRY(launch_fp(a, t.strip, t.waves, s));
+    {
+        ProfScope ps("fp", s);
+        HIP_TRY(launch_fp(a, t.strip, t.waves, s));
+    }
     const int Wp = geom->width + kPadLo + kPadHi;
-    HIP_TRY(launch_unstage_add(static_cast<const float*>(d->adjoint.p), proj_out, geom->n_proj, geom->width,
-                               geom->height, Wp, a.proj_stride / 4, accumulate, s));
+    {
+        ProfScope ps("unstage", s);
+        HIP_TRY(launch_unstage_add(static_cast<const float*>(d->adjoint.p), proj_out, geom->n_proj, geom->width,
+                                   geom->height, Wp, a.proj_stride / 4, accumulate, s));
+    }
     return end_call(*d, s);
 }
 
@@ -540,6 +617,7 @@ fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width,
     fdk_status st = device_state(&d);
     if (st != FDK_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    ProfScope ps("pack", s);
     HIP_TRY(launch_pack(src, n_proj, width, height, dtype, dst, scale_out, s));
     return FDK_OK;
 }
@@ -603,7 +681,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         for (BatchEntry& b : d->batch_cache) {
             if (b.exec) (void)hipGraphExecDestroy(b.exec);
             release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
-            release(b.coef64); release(b.coef32); release(b.counter);
+            release(b.coef64); release(b.coef_dev); release(b.counter);
         }
         d->batch_cache.clear();
         hipError_t e = ensure(d->batch_staged, stage_total);
@@ -624,7 +702,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
             BatchEntry& b = d->batch_cache.back();
             if (b.exec) (void)hipGraphExecDestroy(b.exec);
             release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
-            release(b.coef64); release(b.coef32); release(b.counter);
+            release(b.coef64); release(b.coef_dev); release(b.counter);
             d->batch_cache.pop_back();
         }
         // host tables
@@ -672,18 +750,18 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         alloc(b.stage, n_scans * sizeof(StageArgs));
         alloc(b.scale_ptrs, (size_t)total_proj * sizeof(float*));
         alloc(b.coef64, coef64.size() * sizeof(double));
-        alloc(b.coef32, (size_t)total_proj * 16 * sizeof(float));
+        alloc(b.coef_dev, (size_t)total_proj * 16 * sizeof(double));
         alloc(b.counter, sizeof(unsigned));
         if (e != hipSuccess) {
             release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
-            release(b.coef64); release(b.coef32); release(b.counter);
+            release(b.coef64); release(b.coef_dev); release(b.counter);
             return fail(FDK_E_NOMEM, "batched tables: %s", hipGetErrorString(e));
         }
         for (int j = 0; j < n_scans; ++j) {
             const fdk_scan& sc = scans[order[j]];
             tiles[j] = make_args(&sc.vol, &sc.proj, esize_of(sc.proj.dtype), t,
                                  static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j],
-                                 static_cast<float*>(b.coef32.p) + (size_t)proj_begin[j] * 16, sc.volume,
+                                 static_cast<double*>(b.coef_dev.p) + (size_t)proj_begin[j] * 16, sc.volume,
                                  out_scales[j], accumulate, sc.proj.dtype);
         }
         auto up = [&](DevBuf& buf, const void* src, size_t n) {
@@ -707,7 +785,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
             hipError_t e1 = launch_stage_batched(static_cast<const StageArgs*>(b.stage.p), n_scans, rows, d->capture_stream);
             hipError_t e2 = launch_fold(static_cast<const double*>(b.coef64.p),
                                         static_cast<const float* const*>(b.scale_ptrs.p),
-                                        static_cast<float*>(b.coef32.p), total_proj, d->capture_stream);
+                                        static_cast<double*>(b.coef_dev.p), total_proj, d->capture_stream);
             hipError_t e3 = launch_reset_counter(static_cast<unsigned*>(b.counter.p), d->capture_stream);
             hipError_t e4 = launch_bp_batched(static_cast<const TileArgs*>(b.tiles.p),
                                               static_cast<const int32_t*>(b.item_begin.p), n_scans,
@@ -721,13 +799,16 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         if (e != hipSuccess) {
             if (b.exec) (void)hipGraphExecDestroy(b.exec);
             release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
-            release(b.coef64); release(b.coef32); release(b.counter);
+            release(b.coef64); release(b.coef_dev); release(b.counter);
             return fail(FDK_E_DEVICE, "batched graph build failed: %s", hipGetErrorString(e));
         }
         d->batch_cache.push_front(std::move(b));
         hit = &d->batch_cache.front();
     }
-    HIP_TRY(hipGraphLaunch(hit->exec, s));
+    {
+        ProfScope ps("batched", s);
+        HIP_TRY(hipGraphLaunch(hit->exec, s));
+    }
     return end_call(*d, s);
 }
 
@@ -828,18 +909,53 @@ fdk_status fdk_release_workspace(void)
     DeviceState& d = it->second;
     HIP_TRY(hipDeviceSynchronize());
     release(d.staged);
-    release(d.coef32);
+    release(d.coef_dev);
     release(d.adjoint);
     for (CoefEntry& c : d.coef_cache) release(c.buf);
     d.coef_cache.clear();
     for (BatchEntry& b : d.batch_cache) {
         if (b.exec) (void)hipGraphExecDestroy(b.exec);
         release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
-        release(b.coef64); release(b.coef32); release(b.counter);
+        release(b.coef64); release(b.coef_dev); release(b.counter);
     }
     d.batch_cache.clear();
     release(d.batch_staged);
     d.have_last = false;
+    return FDK_OK;
+}
+
+fdk_status fdk_profile_enable(int enable)
+{
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (ProfRecord& r : g_prof.records) {
+        (void)hipEventSynchronize(r.end);
+        g_prof.pool.push_back(r.start);
+        g_prof.pool.push_back(r.end);
+    }
+    g_prof.records.clear();
+    g_prof.on = enable != 0;
+    return FDK_OK;
+}
+
+fdk_status fdk_profile_read(const char* kernel, int64_t* launches, double* total_ms)
+{
+    g_last_error.clear();
+    if (kernel == nullptr || launches == nullptr || total_ms == nullptr)
+        return fail(FDK_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lock(g_mu);
+    int64_t n = 0;
+    double ms = 0.0;
+    for (ProfRecord& r : g_prof.records) {
+        if (std::strcmp(r.kind, kernel) != 0) continue;
+        HIP_TRY(hipEventSynchronize(r.end));
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, r.start, r.end));
+        ms += t;
+        ++n;
+    }
+    *launches = n;
+    *total_ms = ms;
     return FDK_OK;
 }
 

@@ -22,7 +22,7 @@ constexpr int kWave = 64;
 // magnitudes of u, v, x, y, z halve.
 struct TileArgs {
     const unsigned char* proj;   // staged padded projections (or adjoint accumulation buffer)
-    const float* coef;           // n_proj x 16 floats: rows u, v, w of the composed matrix
+    const double* coef;          // n_proj x 16 doubles: rows u, v, w of the composed matrix
     float* vol;                  // volume buffer (planes z_begin .. z_begin + z_count)
     uint64_t proj_stride;        // bytes between consecutive staged projections
     int32_t n_proj;
@@ -55,9 +55,9 @@ struct StageArgs {
 hipError_t launch_stage(const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_batched(const StageArgs* dev_args, int n_stacks, int64_t total_rows,
                                 hipStream_t s);
-hipError_t launch_fold(const double* coef64, const float* const* scale_ptrs, float* coef32,
+hipError_t launch_fold(const double* coef64, const float* const* scale_ptrs, double* out,
                        int n_total, hipStream_t s);
-hipError_t launch_fold_single(const double* coef64, const float* scale, float* coef32, int n,
+hipError_t launch_fold_single(const double* coef64, const float* scale, double* out, int n,
                               hipStream_t s);
 hipError_t launch_bp(const TileArgs& a, int strip, int waves, hipStream_t s);
 hipError_t launch_fp(const TileArgs& a, int strip, int waves, hipStream_t s);

@@ -46,12 +46,16 @@ __device__ __forceinline__ int cvt_floor(float x)
     return r;
 }
 
-// Byte offset of tap (i0, j0) in a staged image: ((j0 * Wp + i0) << log2(esize)) + centre.
+// Byte offset of tap (i0, j0) relative to an anchor: ((j0 * Wp + i0) << log2(esize)) + base.
+// (The multiply-add is written out so the compiler cannot re-associate it into
+// a full-rate-unfriendly 32-bit multiply of j0 by the byte pitch.)
 template <typename T>
-__device__ __forceinline__ uint32_t tap_offset(int i0, int j0, int wp, int centre_bytes)
+__device__ __forceinline__ uint32_t tap_offset(int i0, int j0, int wp, int base)
 {
-    const int t = __mul24(j0, wp) + i0;
-    return (uint32_t)((t << (sizeof(T) == 4 ? 2 : 1)) + centre_bytes);
+    int t, off;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(t) : "v"(j0), "s"(wp), "v"(i0));
+    asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(off) : "v"(t), "i"(sizeof(T) == 4 ? 2 : 1), "v"(base));
+    return (uint32_t)off;
 }
 
 // One detector row of the 2x2 tap block: the taps (i0, i0+1) come from one
@@ -110,7 +114,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
 
 struct TilePos {
     int x, y0, zl;
-    float xf, zf;
+    double xd, yd, zd;   // centred voxel indices of the strip start
 };
 
 template <int S, int NW>
@@ -126,9 +130,63 @@ __device__ __forceinline__ TilePos tile_pos(const TileArgs& a, int tile)
     p.x = tx * kWave + lane;
     p.y0 = ty * S;
     p.zl = tz * NW + wave;
-    p.xf = (float)(p.x - a.ctr);
-    p.zf = (float)(a.z_begin + p.zl - a.ctr);
+    p.xd = (double)(p.x - a.ctr);
+    p.yd = (double)(p.y0 - a.ctr);
+    p.zd = (double)(a.z_begin + p.zl - a.ctr);
     return p;
+}
+
+// Per lane and projection: detector coordinates of the strip start in FP64,
+// split into an integer anchor pixel (au, av) and FP32 remainders that are
+// stepped along the strip.  u/w then only has to resolve a few pixels in
+// FP32 instead of the detector half-width, which is what keeps the sampling
+// position accurate to ~1e-5 px at 1248x960.
+struct Strip {
+    float ub, vb, wb;          // u - au w, v - av w, w at the strip start
+    float du, dv, dw;          // steps per voxel along y
+    float lox, hix, loy, hiy;  // clamp range of the remainders (detector border, minus anchor)
+    int base;                  // byte offset of the anchor pixel in a staged image
+};
+
+template <int ES>
+__device__ __forceinline__ Strip strip_setup(const double* c, const TilePos& p, const TileArgs& a, int wp)
+{
+    const double ub = fma(p.xd, c[0], fma(p.yd, c[1], fma(p.zd, c[2], c[3])));
+    const double vb = fma(p.xd, c[4], fma(p.yd, c[5], fma(p.zd, c[6], c[7])));
+    const double wb = fma(p.xd, c[8], fma(p.yd, c[9], fma(p.zd, c[10], c[11])));
+    const float wf = (float)wb;
+    const float rf = __builtin_amdgcn_rcpf(wf);
+    // any integer near u/w will do; clamping keeps the integer math bounded
+    const float fau = fminf(fmaxf(rintf((float)ub * rf), a.lo_x), a.hi_x);
+    const float fav = fminf(fmaxf(rintf((float)vb * rf), a.lo_y), a.hi_y);
+    const double dau = (double)fau, dav = (double)fav;
+    Strip st;
+    st.ub = (float)fma(-dau, wb, ub);
+    st.vb = (float)fma(-dav, wb, vb);
+    st.wb = wf;
+    st.du = (float)fma(-dau, c[9], c[1]);
+    st.dv = (float)fma(-dav, c[9], c[5]);
+    st.dw = (float)c[9];
+    st.lox = a.lo_x - fau;
+    st.hix = a.hi_x - fau;
+    st.loy = a.lo_y - fav;
+    st.hiy = a.hi_y - fav;
+    st.base = ((__mul24((int)fav, wp) + (int)fau) << (ES == 4 ? 2 : 1)) + (int)a.centre_bytes;
+    return st;
+}
+
+// The 12 FP64 coefficients of projection k (16 are stored per projection).
+struct Coef {
+    double c[12];
+};
+
+__device__ __forceinline__ Coef load_coef(const double* tab, int k)
+{
+    Coef r;
+    const double* t = tab + 16 * k;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) r.c[i] = t[i];
+    return r;
 }
 
 // Backprojection of all projections into one tile: 64 x-columns x S y-rows
@@ -136,41 +194,31 @@ __device__ __forceinline__ TilePos tile_pos(const TileArgs& a, int tile)
 template <typename T, int S, int NW>
 __device__ __forceinline__ void bp_tile(const TileArgs& a, int tile)
 {
+    constexpr int ES = sizeof(T);
     const TilePos p = tile_pos<S, NW>(a, tile);
-    float yf[S], acc[S];
+    float acc[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        yf[s] = (float)(p.y0 + s - a.ctr);
-        acc[s] = 0.0f;
-    }
-    const float4* coef = reinterpret_cast<const float4*>(a.coef);
+    for (int s = 0; s < S; ++s) acc[s] = 0.0f;
     const unsigned char* img = a.proj;
     const uint32_t row = a.row_bytes;
-    const int wp = (int)(a.row_bytes / sizeof(T));
-    const int cb = (int)a.centre_bytes;
+    const int wp = (int)(a.row_bytes / ES);
     // coefficients of projection k+1 are fetched while projection k is processed
-    float4 nu = coef[0], nv = coef[1], nw = coef[2];
+    Coef next = load_coef(a.coef, 0);
     for (int k = 0; k < a.n_proj; ++k, img += a.proj_stride) {
-        const float4 cu = nu, cv = nv, cw = nw;
-        if (k + 1 < a.n_proj) {
-            nu = coef[4 * k + 4];
-            nv = coef[4 * k + 5];
-            nw = coef[4 * k + 6];
-        }
-        const float ub = fmaf(p.xf, cu.x, fmaf(p.zf, cu.z, cu.w));
-        const float vb = fmaf(p.xf, cv.x, fmaf(p.zf, cv.z, cv.w));
-        const float wb = fmaf(p.xf, cw.x, fmaf(p.zf, cw.z, cw.w));
+        const Coef cur = next;
+        if (k + 1 < a.n_proj) next = load_coef(a.coef, k + 1);
+        const Strip st = strip_setup<ES>(cur.c, p, a, wp);
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const float u = fmaf(yf[s], cu.y, ub);
-            const float v = fmaf(yf[s], cv.y, vb);
-            const float w = fmaf(yf[s], cw.y, wb);
+            const float u = fmaf((float)s, st.du, st.ub);
+            const float v = fmaf((float)s, st.dv, st.vb);
+            const float w = fmaf((float)s, st.dw, st.wb);
             const float r = __builtin_amdgcn_rcpf(w);
-            const float ix = __builtin_amdgcn_fmed3f(u * r, a.lo_x, a.hi_x);
-            const float iy = __builtin_amdgcn_fmed3f(v * r, a.lo_y, a.hi_y);
-            const float sx = __builtin_amdgcn_fractf(ix), sy = __builtin_amdgcn_fractf(iy);
-            const uint32_t off = tap_offset<T>(cvt_floor(ix), cvt_floor(iy), wp, cb);
+            const float dx = __builtin_amdgcn_fmed3f(u * r, st.lox, st.hix);
+            const float dy = __builtin_amdgcn_fmed3f(v * r, st.loy, st.hiy);
+            const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
+            const uint32_t off = tap_offset<T>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
             const float top = Taps<T>::row(rs, off, 0, sx);
             const float bot = Taps<T>::row(rs, off, row, sx);
             const float val = fmaf(sy, bot - top, top);
@@ -190,8 +238,14 @@ __device__ __forceinline__ void bp_tile(const TileArgs& a, int tile)
     }
 }
 
+// Register budget: longer strips keep more taps in flight, so they are allowed
+// more VGPRs (fewer resident waves per SIMD).
+template <int S>
+constexpr int waves_per_eu() { return S <= 4 ? 8 : S <= 8 ? 6 : S <= 16 ? 4 : 3; }
+
 template <typename T, int S, int NW>
-__global__ __launch_bounds__(kWave * NW) void bp_kernel(TileArgs a)
+__global__ __launch_bounds__(kWave * NW)
+    __attribute__((amdgpu_waves_per_eu(waves_per_eu<S>(), waves_per_eu<S>()))) void bp_kernel(TileArgs a)
 {
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     bp_tile<T, S, NW>(a, tile);
@@ -202,7 +256,8 @@ __global__ __launch_bounds__(kWave * NW) void bp_kernel(TileArgs a)
 // decreasing cost (projection count) on the host, so the tail is made of the
 // cheapest tiles.
 template <int S, int NW>
-__global__ __launch_bounds__(kWave * NW) void bp_batched_kernel(const TileArgs* __restrict__ scans,
+__global__ __launch_bounds__(kWave * NW)
+    __attribute__((amdgpu_waves_per_eu(waves_per_eu<S>(), waves_per_eu<S>()))) void bp_batched_kernel(const TileArgs* __restrict__ scans,
                                                                 const int32_t* __restrict__ item_begin,
                                                                 int n_scans, unsigned* counter,
                                                                 int total_items)
@@ -231,47 +286,45 @@ __global__ __launch_bounds__(kWave * NW) void bp_batched_kernel(const TileArgs* 
 }
 
 // Forward projection (adjoint): every voxel scatters value/w^2 onto its four
-// bilinear taps in a zero-bordered FP32 accumulation image per projection.
-// Voxels whose sample does not touch the detector issue no atomics.
+// bilinear taps in a zero-bordered FP32 accumulation image per projection,
+// with the same strip coordinates as the backprojection.  Voxels whose sample
+// does not touch the detector issue no atomics.
 template <int S, int NW>
-__global__ __launch_bounds__(kWave * NW) void fp_kernel(TileArgs a)
+__global__ __launch_bounds__(kWave * NW)
+    __attribute__((amdgpu_waves_per_eu(waves_per_eu<S>(), waves_per_eu<S>()))) void fp_kernel(TileArgs a)
 {
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const TilePos p = tile_pos<S, NW>(a, tile);
-    float yf[S], xv[S];
+    float xv[S];
     const bool col_ok = p.x < a.L && p.zl < a.z_count;
     const float* in = a.vol + ((int64_t)p.zl * a.L + p.y0) * a.L + p.x;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        yf[s] = (float)(p.y0 + s - a.ctr);
+    for (int s = 0; s < S; ++s)
         xv[s] = (col_ok && p.y0 + s < a.L) ? in[(int64_t)s * a.L] * a.out_scale : 0.0f;
-    }
-    const float4* coef = reinterpret_cast<const float4*>(a.coef);
     const unsigned char* img = a.proj;
     const int row = (int)a.row_bytes;
     const int wp = row / 4;
-    const int cb = (int)a.centre_bytes;
-    const float in_lo_x = a.lo_x + 1.0f, in_hi_x = a.hi_x - 1.0f;
-    const float in_lo_y = a.lo_y + 1.0f, in_hi_y = a.hi_y - 1.0f;
+    Coef next = load_coef(a.coef, 0);
     for (int k = 0; k < a.n_proj; ++k, img += a.proj_stride) {
-        const float4 cu = coef[4 * k + 0];
-        const float4 cv = coef[4 * k + 1];
-        const float4 cw = coef[4 * k + 2];
-        const float ub = fmaf(p.xf, cu.x, fmaf(p.zf, cu.z, cu.w));
-        const float vb = fmaf(p.xf, cv.x, fmaf(p.zf, cv.z, cv.w));
-        const float wb = fmaf(p.xf, cw.x, fmaf(p.zf, cw.z, cw.w));
+        const Coef cur = next;
+        if (k + 1 < a.n_proj) next = load_coef(a.coef, k + 1);
+        const Strip st = strip_setup<4>(cur.c, p, a, wp);
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
+        // a sample touches the detector iff the remainder lies strictly inside
+        // (border + 1) on both axes
+        const float in_lox = st.lox + 1.0f, in_hix = st.hix - 1.0f;
+        const float in_loy = st.loy + 1.0f, in_hiy = st.hiy - 1.0f;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const float u = fmaf(yf[s], cu.y, ub);
-            const float v = fmaf(yf[s], cv.y, vb);
-            const float w = fmaf(yf[s], cw.y, wb);
+            const float u = fmaf((float)s, st.du, st.ub);
+            const float v = fmaf((float)s, st.dv, st.vb);
+            const float w = fmaf((float)s, st.dw, st.wb);
             const float r = __builtin_amdgcn_rcpf(w);
-            const float ix = u * r, iy = v * r;
-            const bool hit = ix > in_lo_x && ix < in_hi_x && iy > in_lo_y && iy < in_hi_y;
+            const float dx = u * r, dy = v * r;
+            const bool hit = dx > in_lox && dx < in_hix && dy > in_loy && dy < in_hiy;
             if (hit && xv[s] != 0.0f) {
-                const float sx = __builtin_amdgcn_fractf(ix), sy = __builtin_amdgcn_fractf(iy);
-                const int off = (int)tap_offset<float>(cvt_floor(ix), cvt_floor(iy), wp, cb);
+                const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
+                const int off = (int)tap_offset<float>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
                 const float val = xv[s] * (r * r);
                 const float b = val * sy, t = val - b;   // row weights times value
                 __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(t - t * sx, rs, off, 0, 0);
@@ -327,30 +380,31 @@ __global__ __launch_bounds__(256) void stage_batched_kernel(const StageArgs* __r
     stage_row(a, row - a.row_begin);
 }
 
-// coef32[p][0..11] = FP32(coef64[p][0..11] / sqrt(scale_p)), FP64 arithmetic:
-// folding the dequantisation factor into the matrix scales w by 1/sqrt(s), so
-// the kernel's 1/w^2 weight carries s while u/w and v/w are untouched.
+// out[p][0..11] = coef64[p][0..11] / sqrt(scale_p) in FP64 (16 doubles per
+// projection): folding the dequantisation factor into the matrix scales w by
+// 1/sqrt(s), so the kernel's 1/w^2 weight carries s while u/w and v/w are
+// untouched.
 __global__ void fold_kernel(const double* __restrict__ coef64, const float* const* __restrict__ scale_ptrs,
-                            float* __restrict__ coef32, int n_total)
+                            double* __restrict__ out, int n_total)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_total * 16) return;
     const int p = t >> 4, c = t & 15;
-    if (c >= 12) { coef32[t] = 0.0f; return; }
+    if (c >= 12) { out[t] = 0.0; return; }
     double f = 1.0;
     if (scale_ptrs != nullptr && scale_ptrs[p] != nullptr) f = 1.0 / sqrt((double)*scale_ptrs[p]);
-    coef32[t] = (float)(coef64[p * 12 + c] * f);
+    out[t] = coef64[p * 12 + c] * f;
 }
 
 __global__ void fold_single_kernel(const double* __restrict__ coef64, const float* __restrict__ scale,
-                                   float* __restrict__ coef32, int n)
+                                   double* __restrict__ out, int n)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * 16) return;
     const int p = t >> 4, c = t & 15;
-    if (c >= 12) { coef32[t] = 0.0f; return; }
+    if (c >= 12) { out[t] = 0.0; return; }
     const double f = scale != nullptr ? 1.0 / sqrt((double)scale[p]) : 1.0;
-    coef32[t] = (float)(coef64[p * 12 + c] * f);
+    out[t] = coef64[p * 12 + c] * f;
 }
 
 __global__ void reset_counter_kernel(unsigned* c) { *c = 0u; }
@@ -480,7 +534,8 @@ int batched_occupancy_t()
 }
 
 #define FDK_TILE_TABLE(X) \
-    X(2, 1) X(2, 2) X(2, 4) X(4, 1) X(4, 2) X(4, 4) X(8, 1) X(8, 2) X(8, 4) X(16, 1) X(16, 2) X(16, 4)
+    X(2, 1) X(2, 2) X(2, 4) X(4, 1) X(4, 2) X(4, 4) X(8, 1) X(8, 2) X(8, 4) X(16, 1) X(16, 2) X(16, 4) \
+    X(32, 1) X(32, 2) X(32, 4)
 
 }  // namespace
 
@@ -545,7 +600,7 @@ hipError_t launch_stage_batched(const StageArgs* dev_args, int n_stacks, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_fold(const double* coef64, const float* const* scale_ptrs, float* coef32, int n_total,
+hipError_t launch_fold(const double* coef64, const float* const* scale_ptrs, double* coef32, int n_total,
                        hipStream_t s)
 {
     const int threads = n_total * 16;
@@ -554,7 +609,7 @@ hipError_t launch_fold(const double* coef64, const float* const* scale_ptrs, flo
     return hipGetLastError();
 }
 
-hipError_t launch_fold_single(const double* coef64, const float* scale, float* coef32, int n,
+hipError_t launch_fold_single(const double* coef64, const float* scale, double* coef32, int n,
                               hipStream_t s)
 {
     const int threads = n * 16;

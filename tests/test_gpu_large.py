@@ -1,0 +1,114 @@
+"""Full-size parity on sampled voxels: 512^3 and 1024^3 from 496 filtered
+1248x960 projections, in the launch configuration the benchmark times."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic as S
+from tests._common import REL_L2_FP32, ensure_built
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def fdk():
+    ensure_built()
+    import paper_1401_3615_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def c1():
+    carm = S.CArm(496)
+    mats, q = S.filtered_projections(carm, 0, device=DEV)
+    q = q.contiguous()
+    q64 = q.cpu().numpy().astype(np.float64)
+    return carm, mats, q, q64
+
+
+def sample_voxels(L, n, seed):
+    """Seeded random voxels plus the eight corners and the centre."""
+    rng = np.random.default_rng(seed)
+    pts = rng.integers(0, L, size=(n, 3))
+    corners = np.array([[x, y, z] for x in (0, L - 1) for y in (0, L - 1) for z in (0, L - 1)])
+    return np.concatenate([pts, corners, [[L // 2] * 3]]).astype(np.int32)
+
+
+def check_points(vol_gpu, xyz, ref, what, rel=REL_L2_FP32):
+    idx = torch.as_tensor(xyz.astype(np.int64), device=vol_gpu.device)
+    got = vol_gpu[idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    err = oracle.rel_l2(got, ref)
+    print(f"{what}: rel L2 over {len(ref)} sampled voxels {err:.3e}")
+    assert np.all(np.isfinite(got))
+    assert err <= rel, f"{what}: rel L2 {err:.3e} > {rel:.1e}"
+    return err
+
+
+def test_512_fp32_sampled(fdk, c1):
+    carm, mats, q, q64 = c1
+    L, voxel = 512, 0.5
+    xyz = sample_voxels(L, 3000, 11)
+    out = fdk.backproject(q, fdk.Geometry(mats, carm.width, carm.height), fdk.Volume(L, voxel))
+    torch.cuda.synchronize()
+    ref = oracle.backproject_points(xyz, voxel, mats, q64, L=L)
+    check_points(out, xyz, ref, "512^3 fp32")
+
+
+def test_512_fp32_full_planes(fdk, c1):
+    """Whole planes: plane 7 lies outside the cone for every projection (all
+    zero), plane 80 is partly clipped, plane 300 crosses the clipped corners."""
+    carm, mats, q, q64 = c1
+    L, voxel = 512, 0.5
+    out = fdk.backproject(q, fdk.Geometry(mats, carm.width, carm.height), fdk.Volume(L, voxel))
+    torch.cuda.synchronize()
+    ref7 = oracle.backproject(L, voxel, mats, q64, z_range=(7, 1))[0]
+    assert np.all(ref7 == 0.0)
+    assert torch.count_nonzero(out[7]).item() == 0
+    for z in (80, 300):
+        ref = oracle.backproject(L, voxel, mats, q64, z_range=(z, 1))[0]
+        got = out[z].double().cpu().numpy()
+        err = oracle.rel_l2(got, ref)
+        print(f"512^3 plane {z}: rel L2 {err:.3e}")
+        assert err <= REL_L2_FP32
+
+
+@pytest.mark.parametrize("dtype,total_bound", [(torch.float16, 1e-3), (torch.bfloat16, 1e-2)])
+def test_512_packed_sampled(fdk, c1, dtype, total_bound):
+    """FP16/BF16 storage: the kernel error (against the oracle run on the
+    dequantised values) meets the FP32 bar; the total error against the FP32
+    projections is the storage error, bounded loosely and printed."""
+    carm, mats, q, q64 = c1
+    L, voxel = 512, 0.5
+    qp, sc = fdk.pack_projections(q, dtype)
+    out = fdk.backproject(qp, fdk.Geometry(mats, carm.width, carm.height), fdk.Volume(L, voxel), scale=sc)
+    torch.cuda.synchronize()
+    xyz = sample_voxels(L, 2000, 12)
+    deq = qp.double().cpu().numpy() * sc.double().cpu().numpy()[:, None, None]
+    ref_k = oracle.backproject_points(xyz, voxel, mats, deq, L=L)
+    check_points(out, xyz, ref_k, f"512^3 {dtype} kernel error")
+    ref = oracle.backproject_points(xyz, voxel, mats, q64, L=L)
+    check_points(out, xyz, ref, f"512^3 {dtype} total error", rel=total_bound)
+
+
+def test_1024_slabs_sampled(fdk, c1):
+    """1024^3 at 0.25 mm processed as four z-slabs into one 4 GiB buffer."""
+    carm, mats, q, q64 = c1
+    L, voxel = 1024, 0.25
+    geom = fdk.Geometry(mats, carm.width, carm.height)
+    base = fdk.Volume(L, voxel)
+    out = torch.empty((L, L, L), device=DEV)
+    for z0 in range(0, L, 256):
+        fdk.backproject(q, geom, base.slab(z0, 256), out=out[z0:z0 + 256])
+    torch.cuda.synchronize()
+    xyz = sample_voxels(L, 1500, 13)
+    ref = oracle.backproject_points(xyz, voxel, mats, q64, L=L)
+    check_points(out, xyz, ref, "1024^3 slabs fp32")
+    # one whole-volume launch gives the same values at the sampled voxels
+    whole = fdk.backproject(q, geom, base)
+    torch.cuda.synchronize()
+    idx = torch.as_tensor(xyz.astype(np.int64), device=DEV)
+    assert torch.equal(whole[idx[:, 2], idx[:, 1], idx[:, 0]], out[idx[:, 2], idx[:, 1], idx[:, 0]])
