@@ -160,26 +160,32 @@ fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width,
                                 int32_t height, int32_t dtype, void* dst,
                                 float* scale_out, void* stream);
 
-/* Tile shape of the backprojection kernel: each lane of a 64-wide wavefront
- * owns one x column and a strip of `strip` voxels along y; a workgroup stacks
- * `waves` wavefronts along z.  strip in {2, 4, 8, 16, 32}, waves in {1, 2, 4}.
- * fdk_set_tile pins the shape for a dtype (0, 0 restores automatic choice from
- * the tuning table); fdk_get_tile reports the shape a call with this grid and
- * dtype would use. */
-fdk_status fdk_set_tile(int32_t dtype, int32_t strip, int32_t waves);
-fdk_status fdk_get_tile(const fdk_volume* vol, int32_t dtype, int32_t* strip,
-                        int32_t* waves);
+/* Tile shape and staged layout of the backprojection kernel: a 64-wide
+ * wavefront owns an 8 x 8 patch of (x, y) columns and each lane a strip of
+ * `strip` voxels along z; a workgroup holds `waves` patches (1 x 1, 2 x 1 or
+ * 2 x 2); strip in {2, 4, 8, 16, 32}, waves in {1, 2, 4}.  layout 0 stages each
+ * projection as a zero-bordered image; layout 1 stores with every staged
+ * pixel its whole 2x2 bilinear block (four times the staging memory, one load
+ * per sample); layout 2 stores with every pixel its right neighbour (twice the
+ * memory, aligned row loads).
+ * fdk_set_tile pins the choice for a dtype (strip = waves = 0 restores the
+ * automatic choice from the tuning table); fdk_get_tile reports what a call
+ * with this grid and dtype would use. */
+fdk_status fdk_set_tile(int32_t dtype, int32_t strip, int32_t waves, int32_t layout);
+fdk_status fdk_get_tile(const fdk_volume* vol, int32_t dtype, int32_t* strip, int32_t* waves,
+                        int32_t* layout);
 
-/* Tuning table: entries (dtype, size class) -> tile shape, as written by the
- * autotuner.  fdk_load_tuning reads a file of lines "dtype class strip waves"
- * ('#' starts a comment); size class = floor(log2(L)).  Entries for other
- * library ABI versions are rejected (the file's first line must read
- * "fdk-tuning <FDK_ABI_VERSION> gfx950").  Returns the number of entries read
- * or a negative fdk_status.  fdk_set_tuning_entry sets one entry; strip = waves
- * = 0 removes it. */
+/* Tuning table: entries (dtype, size class) -> tile shape and layout, as
+ * written by the autotuner.  fdk_load_tuning reads a file of lines
+ * "dtype class strip waves layout" ('#' starts a comment); size class =
+ * floor(log2(L)).  A file for another library ABI version or device is
+ * rejected (its first line must read "fdk-tuning <FDK_ABI_VERSION> gfx950").
+ * Returns the number of entries read or a negative fdk_status.
+ * fdk_set_tuning_entry sets one entry; strip = waves = 0 removes it.  The
+ * environment variable FDK_TUNING_FILE names a file loaded on first use. */
 int32_t fdk_load_tuning(const char* path);
-fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip,
-                                int32_t waves);
+fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip, int32_t waves,
+                                int32_t layout);
 
 /* Host-side check of a call's arguments: the validation fdk_backproject
  * performs, without touching the GPU. */

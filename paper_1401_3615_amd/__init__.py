@@ -72,10 +72,11 @@ def load():
         "fdk_forwardproject": ([pv, vp, pp, vp, ctypes.c_int, vp], ctypes.c_int),
         "fdk_backproject_batched": ([ps, i32, ctypes.c_int, vp], ctypes.c_int),
         "fdk_pack_projections": ([vp, i32, i32, i32, i32, vp, vp, vp], ctypes.c_int),
-        "fdk_set_tile": ([i32, i32, i32], ctypes.c_int),
-        "fdk_get_tile": ([pv, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
+        "fdk_set_tile": ([i32, i32, i32, i32], ctypes.c_int),
+        "fdk_get_tile": ([pv, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
+                         ctypes.c_int),
         "fdk_load_tuning": ([ctypes.c_char_p], i32),
-        "fdk_set_tuning_entry": ([i32, i32, i32, i32], ctypes.c_int),
+        "fdk_set_tuning_entry": ([i32, i32, i32, i32, i32], ctypes.c_int),
         "fdk_validate": ([pv, pp, ctypes.c_int], ctypes.c_int),
         "fdk_release_workspace": ([], ctypes.c_int),
         "fdk_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -268,15 +269,18 @@ def pack_projections(proj: torch.Tensor, dtype=torch.float16, stream=None):
     return packed, scale
 
 
-def set_tile(dtype: int, strip: int, waves: int) -> None:
-    _check(load().fdk_set_tile(dtype, strip, waves))
+def set_tile(dtype: int, strip: int, waves: int, layout: int = 0) -> None:
+    """Pin (strip, waves, layout) for a dtype; (0, 0) restores the automatic choice."""
+    _check(load().fdk_set_tile(dtype, strip, waves, layout))
 
 
-def get_tile(vol: Volume, dtype: int = F32) -> tuple[int, int]:
-    s, w = ctypes.c_int32(), ctypes.c_int32()
+def get_tile(vol: Volume, dtype: int = F32) -> tuple[int, int, int]:
+    """(strip, waves, layout) a call with this grid and dtype would use."""
+    s, w, lay = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     v = vol.c()
-    _check(load().fdk_get_tile(ctypes.byref(v), dtype, ctypes.byref(s), ctypes.byref(w)))
-    return s.value, w.value
+    _check(load().fdk_get_tile(ctypes.byref(v), dtype, ctypes.byref(s), ctypes.byref(w),
+                               ctypes.byref(lay)))
+    return s.value, w.value, lay.value
 
 
 def load_tuning(path: str) -> int:
@@ -286,8 +290,8 @@ def load_tuning(path: str) -> int:
     return n
 
 
-def set_tuning_entry(dtype: int, size_class: int, strip: int, waves: int) -> None:
-    _check(load().fdk_set_tuning_entry(dtype, size_class, strip, waves))
+def set_tuning_entry(dtype: int, size_class: int, strip: int, waves: int, layout: int = 0) -> None:
+    _check(load().fdk_set_tuning_entry(dtype, size_class, strip, waves, layout))
 
 
 def validate(geom: Geometry, vol: Volume, need_data: bool = False, dtype: int = F32) -> None:

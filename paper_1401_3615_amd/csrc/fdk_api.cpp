@@ -46,6 +46,10 @@ constexpr int kMaxScans = 4096;
 
 int esize_of(int dtype) { return dtype == FDK_F32 ? 4 : 2; }
 
+// Staged row length in pixels: detector plus zero border, rounded up to 8
+// pixels so that every row starts 16-byte aligned.
+int staged_pitch(int W) { return (W + kPadLo + kPadHi + 7) & ~7; }
+
 // ------------------------------------------------------------------ validation
 fdk_status check_volume(const fdk_volume* v)
 {
@@ -76,7 +80,7 @@ fdk_status check_proj(const fdk_projections* p, bool need_data)
         if (p->data == nullptr) return fail(FDK_E_INVALID_ARG, "projection data is NULL");
     }
     const int es = need_data ? esize_of(p->dtype) : 4;
-    const int64_t wp = (int64_t)p->width + kPadLo + kPadHi;
+    const int64_t wp = (int64_t)staged_pitch(p->width);
     const int64_t hp = (int64_t)p->height + kPadLo + kPadHi;
     // staged image offsets are signed 32-bit, row pitch a 24-bit multiplier
     if (wp * hp * es >= (int64_t(1) << 31) || wp >= (int64_t(1) << 23) || hp >= (int64_t(1) << 23))
@@ -210,11 +214,11 @@ struct ProfScope {
 };
 
 // ------------------------------------------------------------------ tiles
-struct TileShape { int strip, waves; };
+struct TileShape { int strip, waves, layout; };
 
 struct Tuning {
     std::map<std::pair<int, int>, TileShape> table;  // (dtype, size class) -> shape
-    TileShape forced[3] = {{0, 0}, {0, 0}, {0, 0}};
+    TileShape forced[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     bool env_loaded = false;
 };
 
@@ -225,17 +229,19 @@ int size_class(int L)
     return c;
 }
 
-// Built-in choice when no tuning entry applies: the longest strip (fewer
-// per-projection set-ups per voxel) that still gives ~4 workgroups per CU on
-// a 256-CU device.
-TileShape default_tile(int L)
+// Built-in choice when no tuning entry applies: four 8x8 patches per
+// workgroup and the longest strip (fewer per-projection set-ups per voxel)
+// that still gives ~4 workgroups per CU on a 256-CU device; FP32 stages the
+// tile footprint in LDS, FP16/BF16 gather whole 2x2 blocks (8 bytes) per load.
+TileShape default_tile(int L, int dtype)
 {
+    const int layout = dtype == FDK_F32 ? 3 : 1;
     const int64_t want = 1024;
-    for (int strip : {32, 16, 8, 4}) {
-        const int64_t tiles = (int64_t)((L + 63) / 64) * ((L + strip - 1) / strip) * ((L + 1) / 2);
-        if (tiles >= want) return {strip, 2};
+    for (int strip : {16, 8, 4}) {
+        const int64_t tiles = (int64_t)((L + 15) / 16) * ((L + 15) / 16) * ((L + strip - 1) / strip);
+        if (tiles >= want) return {strip, 4, layout};
     }
-    return {2, 2};
+    return {2, 4, layout};
 }
 
 // ------------------------------------------------------------------ device state
@@ -287,7 +293,7 @@ struct DeviceState {
     bool arch_ok = false;
     int num_cus = 0;
     std::string arch;
-    DevBuf staged, coef_dev, adjoint;
+    DevBuf staged, coef_dev, adjoint, windows;
     std::list<CoefEntry> coef_cache;   // most recent first
     hipStream_t last_stream = nullptr;
     bool have_last = false;
@@ -394,16 +400,35 @@ fdk_status coef_table(DeviceState& d, const fdk_volume* v, const fdk_projections
     return FDK_OK;
 }
 
+// Bytes of one staged pixel: the source element (plain), its 2x2 block (quad)
+// or its pair of row taps (pair).
+int pixel_bytes(int esize, int layout) { return layout == 1 ? 4 * esize : layout == 2 ? 2 * esize : esize; }
+// Layout 3 (LDS tiles) reads the plain staged image.
+int staged_layout(int layout) { return layout == 3 ? 0 : layout; }
+// The persistent batched kernel gathers from staged images; layout 3 maps to
+// the plain gather there.
+int batched_layout(int layout) { return layout == 3 ? 0 : layout; }
+
+// The quad layout multiplies the staged image by four; images whose quad form
+// would not fit 31-bit offsets use the plain layout.
+TileShape fit_layout(TileShape t, const fdk_projections* p, int esize)
+{
+    const int64_t px = (int64_t)staged_pitch(p->width) * (p->height + kPadLo + kPadHi);
+    if (t.layout != 0 && px * pixel_bytes(esize, t.layout) >= (int64_t(1) << 31)) t.layout = 0;
+    return t;
+}
+
 TileShape pick_tile(int L, int dtype)
 {
     const TileShape f = g_tune.forced[dtype];
     if (f.strip > 0) return f;
     auto it = g_tune.table.find({dtype, size_class(L)});
     if (it != g_tune.table.end()) return it->second;
-    return default_tile(L);
+    return default_tile(L, dtype);
 }
 
 void load_env_tuning();
+
 
 TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, TileShape t,
                    const unsigned char* staged, const double* coef_dev, float* vol, float out_scale,
@@ -412,8 +437,10 @@ TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, Til
     TileArgs a;
     std::memset(&a, 0, sizeof(a));
     const int W = p->width, H = p->height;
-    const int Wp = W + kPadLo + kPadHi, Hp = H + kPadLo + kPadHi;
+    const int Wp = staged_pitch(W), Hp = H + kPadLo + kPadHi;
     const int cu = W / 2, cv = H / 2;
+    esize = pixel_bytes(esize, staged_layout(t.layout));
+    a.layout = t.layout;
     a.proj = staged;
     a.coef = coef_dev;
     a.vol = vol;
@@ -433,10 +460,15 @@ TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, Til
     a.hi_y = (float)(H - 1 + kPadLo - cv);
     a.out_scale = out_scale;
     a.accumulate = accumulate ? 1 : 0;
-    a.tiles_x = (v->L + kWave - 1) / kWave;
-    a.tiles_y = (v->L + t.strip - 1) / t.strip;
-    a.tiles_z = (v->z_count + t.waves - 1) / t.waves;
+    // a workgroup covers (8 bx) x (8 by) columns and `strip` planes
+    const int bx = t.waves >= 2 ? 2 : 1, by = t.waves / bx;
+    a.tiles_x = (v->L + 8 * bx - 1) / (8 * bx);
+    a.tiles_y = (v->L + 8 * by - 1) / (8 * by);
+    a.tiles_z = (v->z_count + t.strip - 1) / t.strip;
     a.dtype = dtype;
+    a.cu = cu;
+    a.cv = cv;
+    a.win = nullptr;
     return a;
 }
 
@@ -447,24 +479,27 @@ fdk_status check_grid(const TileArgs& a)
     return FDK_OK;
 }
 
-uint64_t staged_bytes(const fdk_projections* p, int esize)
+uint64_t staged_bytes(const fdk_projections* p, int esize, int layout)
 {
-    const uint64_t img = (uint64_t)(p->width + kPadLo + kPadHi) * (p->height + kPadLo + kPadHi) * esize;
+    esize = pixel_bytes(esize, staged_layout(layout));
+    const uint64_t img = (uint64_t)staged_pitch(p->width) * (p->height + kPadLo + kPadHi) * esize;
     return (uint64_t)p->n_proj * ((img + 255) & ~uint64_t(255));
 }
 
-StageArgs make_stage(const fdk_projections* p, int esize, unsigned char* dst, int64_t row_begin)
+StageArgs make_stage(const fdk_projections* p, int esize, int layout, unsigned char* dst, int64_t row_begin)
 {
     StageArgs s;
+    layout = staged_layout(layout);
+    s.layout = layout;
     s.src = p->data;
     s.dst = dst;
     s.n = p->n_proj;
     s.W = p->width;
     s.H = p->height;
-    s.Wp = p->width + kPadLo + kPadHi;
+    s.Wp = staged_pitch(p->width);
     s.Hp = p->height + kPadLo + kPadHi;
     s.esize = esize;
-    const uint64_t img = (uint64_t)s.Wp * s.Hp * esize;
+    const uint64_t img = (uint64_t)s.Wp * s.Hp * pixel_bytes(esize, layout);
     s.proj_stride = (img + 255) & ~uint64_t(255);
     s.row_begin = row_begin;
     return s;
@@ -519,7 +554,7 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     std::lock_guard<std::mutex> lock(g_mu);
     load_env_tuning();
     const int es = esize_of(proj->dtype);
-    const TileShape t = pick_tile(vol->L, proj->dtype);
+    const TileShape t = fit_layout(pick_tile(vol->L, proj->dtype), proj, es);
     TileArgs probe = make_args(vol, proj, es, t, nullptr, nullptr, volume, 1.0f, accumulate, proj->dtype);
     if ((st = check_grid(probe)) != FDK_OK) return st;
 
@@ -527,7 +562,7 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     if ((st = device_state(&d)) != FDK_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = begin_call(*d, s)) != FDK_OK) return st;
-    hipError_t e = ensure(d->staged, staged_bytes(proj, es));
+    hipError_t e = ensure(d->staged, staged_bytes(proj, es, t.layout));
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "staging workspace: %s", hipGetErrorString(e));
     e = ensure(d->coef_dev, (size_t)proj->n_proj * 16 * sizeof(double));
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "coefficient workspace: %s", hipGetErrorString(e));
@@ -535,7 +570,7 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     float out_scale = 1.0f;
     if ((st = coef_table(*d, vol, proj, s, &coef64, &out_scale)) != FDK_OK) return st;
 
-    StageArgs sa = make_stage(proj, es, static_cast<unsigned char*>(d->staged.p), 0);
+    StageArgs sa = make_stage(proj, es, t.layout, static_cast<unsigned char*>(d->staged.p), 0);
     {
         ProfScope ps("stage", s);
         HIP_TRY(launch_stage(sa, s));
@@ -546,6 +581,14 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     }
     TileArgs a = make_args(vol, proj, es, t, static_cast<unsigned char*>(d->staged.p),
                            static_cast<double*>(d->coef_dev.p), volume, out_scale, accumulate, proj->dtype);
+    if (t.layout == 3) {
+        const uint64_t nwin = (uint64_t)a.tiles_x * a.tiles_y * a.tiles_z * proj->n_proj;
+        e = ensure(d->windows, nwin * sizeof(Win));
+        if (e != hipSuccess) return fail(FDK_E_NOMEM, "window table: %s", hipGetErrorString(e));
+        a.win = static_cast<const Win*>(d->windows.p);
+        ProfScope ps("window", s);
+        HIP_TRY(launch_window(a, t.strip, t.waves, static_cast<Win*>(d->windows.p), s));
+    }
     {
         ProfScope ps("bp", s);
         HIP_TRY(launch_bp(a, t.strip, t.waves, s));
@@ -562,7 +605,8 @@ fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const 
     if (proj_out == nullptr) return fail(FDK_E_INVALID_ARG, "projection output is NULL");
     std::lock_guard<std::mutex> lock(g_mu);
     load_env_tuning();
-    const TileShape t = pick_tile(vol->L, FDK_F32);
+    TileShape t = pick_tile(vol->L, FDK_F32);
+    t.layout = 0;   // the adjoint accumulates into a plain zero-bordered image
     TileArgs probe = make_args(vol, geom, 4, t, nullptr, nullptr, nullptr, 1.0f, 0, FDK_F32);
     if ((st = check_grid(probe)) != FDK_OK) return st;
 
@@ -570,7 +614,7 @@ fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const 
     if ((st = device_state(&d)) != FDK_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = begin_call(*d, s)) != FDK_OK) return st;
-    const uint64_t bytes = staged_bytes(geom, 4);
+    const uint64_t bytes = staged_bytes(geom, 4, 0);
     hipError_t e = ensure(d->adjoint, bytes);
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "adjoint workspace: %s", hipGetErrorString(e));
     e = ensure(d->coef_dev, (size_t)geom->n_proj * 16 * sizeof(double));
@@ -594,7 +638,7 @@ fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const 
         ProfScope ps("fp", s);
         HIP_TRY(launch_fp(a, t.strip, t.waves, s));
     }
-    const int Wp = geom->width + kPadLo + kPadHi;
+    const int Wp = staged_pitch(geom->width);
     {
         ProfScope ps("unstage", s);
         HIP_TRY(launch_unstage_add(static_cast<const float*>(d->adjoint.p), proj_out, geom->n_proj, geom->width,
@@ -650,6 +694,10 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
     std::string key;
     auto put = [&key](const void* x, size_t n) { key.append(static_cast<const char*>(x), n); };
     put(&t, sizeof(t));
+    for (int dt = 0; dt < 3; ++dt) {
+        const int lay = batched_layout(pick_tile(maxL, dt).layout);
+        put(&lay, sizeof(int));
+    }
     put(&accumulate, sizeof(int));
     for (int i = 0; i < n_scans; ++i) {
         const fdk_scan& sc = scans[i];
@@ -671,7 +719,9 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
     for (int j = 0; j < n_scans; ++j) {
         const int i = order[j];
         stage_off[j] = stage_total;
-        stage_total += staged_bytes(&scans[i].proj, esize_of(scans[i].proj.dtype));
+        const int es_i = esize_of(scans[i].proj.dtype);
+        stage_total += staged_bytes(&scans[i].proj, es_i,
+                                    batched_layout(fit_layout(pick_tile(maxL, scans[i].proj.dtype), &scans[i].proj, es_i).layout));
     }
 
     if ((st = begin_call(*d, s)) != FDK_OK) return st;
@@ -731,10 +781,12 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
                 scale_ptrs.push_back(sc.proj.scale ? sc.proj.scale + k : nullptr);
             out_scales[j] = c.out_scale;
             const int es = esize_of(sc.proj.dtype);
-            stages[j] = make_stage(&sc.proj, es, static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j], rows);
+            TileShape ts = t;
+            ts.layout = batched_layout(fit_layout(pick_tile(maxL, sc.proj.dtype), &sc.proj, es).layout);
+            stages[j] = make_stage(&sc.proj, es, ts.layout, static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j], rows);
             rows += (int64_t)sc.proj.n_proj * stages[j].Hp;
             item_begin[j] = (int32_t)items;
-            TileArgs probe = make_args(&sc.vol, &sc.proj, es, t, nullptr, nullptr, nullptr, 1.0f, 0, sc.proj.dtype);
+            TileArgs probe = make_args(&sc.vol, &sc.proj, es, ts, nullptr, nullptr, nullptr, 1.0f, 0, sc.proj.dtype);
             items += (int64_t)probe.tiles_x * probe.tiles_y * probe.tiles_z;
             if (items > 0x7fffffffLL) return fail(FDK_E_INVALID_ARG, "batch too large for one launch");
         }
@@ -759,7 +811,9 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         }
         for (int j = 0; j < n_scans; ++j) {
             const fdk_scan& sc = scans[order[j]];
-            tiles[j] = make_args(&sc.vol, &sc.proj, esize_of(sc.proj.dtype), t,
+            TileShape ts = t;
+            ts.layout = batched_layout(fit_layout(pick_tile(maxL, sc.proj.dtype), &sc.proj, esize_of(sc.proj.dtype)).layout);
+            tiles[j] = make_args(&sc.vol, &sc.proj, esize_of(sc.proj.dtype), ts,
                                  static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j],
                                  static_cast<double*>(b.coef_dev.p) + (size_t)proj_begin[j] * 16, sc.volume,
                                  out_scales[j], accumulate, sc.proj.dtype);
@@ -812,36 +866,40 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
     return end_call(*d, s);
 }
 
-fdk_status fdk_set_tile(int32_t dtype, int32_t strip, int32_t waves)
+fdk_status fdk_set_tile(int32_t dtype, int32_t strip, int32_t waves, int32_t layout)
 {
     g_last_error.clear();
     if (dtype < 0 || dtype > 2) return fail(FDK_E_UNSUPPORTED, "unknown dtype %d", dtype);
     std::lock_guard<std::mutex> lock(g_mu);
     if (strip == 0 && waves == 0) {
-        g_tune.forced[dtype] = {0, 0};
+        g_tune.forced[dtype] = {0, 0, 0};
         return FDK_OK;
     }
     if (!supported_tile(strip, waves)) return fail(FDK_E_INVALID_ARG, "tile %dx%d not compiled", strip, waves);
-    g_tune.forced[dtype] = {strip, waves};
+    if (layout < 0 || layout > 3) return fail(FDK_E_INVALID_ARG, "layout %d", layout);
+    g_tune.forced[dtype] = {strip, waves, layout};
     return FDK_OK;
 }
 
-fdk_status fdk_get_tile(const fdk_volume* vol, int32_t dtype, int32_t* strip, int32_t* waves)
+fdk_status fdk_get_tile(const fdk_volume* vol, int32_t dtype, int32_t* strip, int32_t* waves,
+                        int32_t* layout)
 {
     g_last_error.clear();
     fdk_status st = check_volume(vol);
     if (st != FDK_OK) return st;
     if (dtype < 0 || dtype > 2) return fail(FDK_E_UNSUPPORTED, "unknown dtype %d", dtype);
-    if (strip == nullptr || waves == nullptr) return fail(FDK_E_INVALID_ARG, "NULL output");
+    if (strip == nullptr || waves == nullptr || layout == nullptr) return fail(FDK_E_INVALID_ARG, "NULL output");
     std::lock_guard<std::mutex> lock(g_mu);
     load_env_tuning();
     const TileShape t = pick_tile(vol->L, dtype);
     *strip = t.strip;
     *waves = t.waves;
+    *layout = t.layout;
     return FDK_OK;
 }
 
-fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip, int32_t waves)
+fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip, int32_t waves,
+                                int32_t layout)
 {
     g_last_error.clear();
     if (dtype < 0 || dtype > 2) return fail(FDK_E_UNSUPPORTED, "unknown dtype %d", dtype);
@@ -852,7 +910,8 @@ fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip
         return FDK_OK;
     }
     if (!supported_tile(strip, waves)) return fail(FDK_E_INVALID_ARG, "tile %dx%d not compiled", strip, waves);
-    g_tune.table[{dtype, size_class}] = {strip, waves};
+    if (layout < 0 || layout > 3) return fail(FDK_E_INVALID_ARG, "layout %d", layout);
+    g_tune.table[{dtype, size_class}] = {strip, waves, layout};
     return FDK_OK;
 }
 
@@ -881,13 +940,13 @@ int32_t fdk_load_tuning(const char* path)
             }
             continue;
         }
-        int dt, cls, s, w;
-        if (std::sscanf(line, "%d %d %d %d", &dt, &cls, &s, &w) == 4) {
-            if (dt < 0 || dt > 2 || cls < 0 || cls > 15 || !supported_tile(s, w)) {
+        int dt, cls, s, w, lay;
+        if (std::sscanf(line, "%d %d %d %d %d", &dt, &cls, &s, &w, &lay) == 5) {
+            if (dt < 0 || dt > 2 || cls < 0 || cls > 15 || !supported_tile(s, w) || lay < 0 || lay > 3) {
                 std::fclose(f);
-                return fail(FDK_E_INVALID_ARG, "%s: bad entry '%d %d %d %d'", path, dt, cls, s, w);
+                return fail(FDK_E_INVALID_ARG, "%s: bad entry '%d %d %d %d %d'", path, dt, cls, s, w, lay);
             }
-            entries.push_back({{dt, cls}, {s, w}});
+            entries.push_back({{dt, cls}, {s, w, lay}});
             ++n;
         }
     }
@@ -911,6 +970,7 @@ fdk_status fdk_release_workspace(void)
     release(d.staged);
     release(d.coef_dev);
     release(d.adjoint);
+    release(d.windows);
     for (CoefEntry& c : d.coef_cache) release(c.buf);
     d.coef_cache.clear();
     for (BatchEntry& b : d.batch_cache) {

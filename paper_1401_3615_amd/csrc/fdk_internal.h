@@ -15,6 +15,13 @@ constexpr int kPadLo = 2;
 constexpr int kPadHi = 3;
 constexpr int kWave = 64;
 
+// Window of staged (zero-bordered) pixels that one workgroup tile needs from
+// one projection, inclusive bounds; i0 > i1 means every tap is off the
+// detector and the projection is skipped for that tile (clipping).
+struct Win {
+    int16_t i0, i1, j0, j1;
+};
+
 // Per-scan arguments of the backprojection / forward-projection tile body.
 // Coordinates inside the kernels are centred: the voxel index is offset by
 // `ctr` on every axis and the detector column/row by (cu, cv) = (W/2, H/2),
@@ -38,7 +45,9 @@ struct TileArgs {
     int32_t accumulate;
     int32_t tiles_x, tiles_y, tiles_z;
     int32_t dtype;               // fdk_dtype of the staged images
-    int32_t pad_;
+    int32_t layout;              // 0 plain, 1 quad, 2 pair (global gathers), 3 LDS tiles
+    const Win* win;              // layout 3: n_tiles x n_proj windows
+    int32_t cu, cv;              // integer detector centre (W/2, H/2)
 };
 
 // One projection stack to stage into the padded layout.
@@ -47,7 +56,8 @@ struct StageArgs {
     unsigned char* dst;          // staged images, proj_stride apart
     uint64_t proj_stride;        // bytes
     int32_t n, W, H, Wp, Hp;
-    int32_t esize;               // 2 or 4
+    int32_t esize;               // 2 or 4 (bytes of one source pixel)
+    int32_t layout;              // 0: plain, 1: quad (2x2 block per staged pixel)
     int64_t row_begin;           // first global row index of this stack (batched staging)
 };
 
@@ -70,6 +80,7 @@ hipError_t launch_unstage_add(const float* padded, float* out, int n, int W, int
                               uint64_t stride_elems, int accumulate, hipStream_t s);
 hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* dst, float* scale,
                        hipStream_t s);
+hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, hipStream_t s);
 int supported_tile(int strip, int waves);
 int batched_blocks_per_cu(int strip, int waves);
 

@@ -46,15 +46,16 @@ __device__ __forceinline__ int cvt_floor(float x)
     return r;
 }
 
-// Byte offset of tap (i0, j0) relative to an anchor: ((j0 * Wp + i0) << log2(esize)) + base.
+// Byte offset of staged pixel (i0, j0) relative to an anchor:
+// ((j0 * Wp + i0) << SHIFT) + base, SHIFT = log2(bytes per staged pixel).
 // (The multiply-add is written out so the compiler cannot re-associate it into
-// a full-rate-unfriendly 32-bit multiply of j0 by the byte pitch.)
-template <typename T>
+// a quarter-rate 32-bit multiply of j0 by the byte pitch.)
+template <int SHIFT>
 __device__ __forceinline__ uint32_t tap_offset(int i0, int j0, int wp, int base)
 {
     int t, off;
     asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(t) : "v"(j0), "s"(wp), "v"(i0));
-    asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(off) : "v"(t), "i"(sizeof(T) == 4 ? 2 : 1), "v"(base));
+    asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(off) : "v"(t), "i"(SHIFT), "v"(base));
     return (uint32_t)off;
 }
 
@@ -101,6 +102,88 @@ template <> struct Taps<bf16_t> {
     }
 };
 
+// The bilinear sample at fraction (sx, sy) inside the 2x2 tap block whose
+// first tap sits at byte offset `off`.  Three staged layouts:
+//   plain (LAY 0): the detector image itself, one (unaligned) load per tap row;
+//   quad  (LAY 1): every staged pixel holds its whole 2x2 block
+//                  (I[j][i], I[j][i+1], I[j+1][i], I[j+1][i+1]), so one aligned
+//                  load per sample fetches all four taps;
+//   pair  (LAY 2): every staged pixel holds (I[j][i], I[j][i+1]), one aligned
+//                  load per tap row.
+template <typename T, int LAY> struct Sampler;
+
+template <typename T> struct Sampler<T, 0> {
+    static constexpr int kShift = sizeof(T) == 4 ? 2 : 1;
+    static __device__ __forceinline__ float sample(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t row,
+                                                   float sx, float sy)
+    {
+        const float top = Taps<T>::row(r, off, 0, sx);
+        const float bot = Taps<T>::row(r, off, row, sx);
+        return fmaf(sy, bot - top, top);
+    }
+};
+
+template <> struct Sampler<float, 1> {
+    static constexpr int kShift = 4;
+    static __device__ __forceinline__ float sample(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t,
+                                                   float sx, float sy)
+    {
+        // four adjacent dword loads, fused by the compiler into one dwordx4
+        const float a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+        const float b = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off + 4, 0, 0));
+        const float c = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off + 8, 0, 0));
+        const float d = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off + 12, 0, 0));
+        const float top = fmaf(sx, b - a, a);
+        const float bot = fmaf(sx, d - c, c);
+        return fmaf(sy, bot - top, top);
+    }
+};
+
+template <> struct Sampler<__half, 1> {
+    static constexpr int kShift = 3;
+    static __device__ __forceinline__ float sample(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t,
+                                                   float sx, float sy)
+    {
+        const uint32_t t0 = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        const uint32_t t1 = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off + 4, 0, 0);
+        const float a = __half2float(__ushort_as_half((unsigned short)(t0 & 0xffffu)));
+        const float b = __half2float(__ushort_as_half((unsigned short)(t0 >> 16)));
+        const float c = __half2float(__ushort_as_half((unsigned short)(t1 & 0xffffu)));
+        const float d = __half2float(__ushort_as_half((unsigned short)(t1 >> 16)));
+        const float top = fmaf(sx, b, fmaf(-sx, a, a));
+        const float bot = fmaf(sx, d, fmaf(-sx, c, c));
+        return fmaf(sy, bot - top, top);
+    }
+};
+
+template <> struct Sampler<bf16_t, 1> {
+    static constexpr int kShift = 3;
+    static __device__ __forceinline__ float sample(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t,
+                                                   float sx, float sy)
+    {
+        const uint32_t t0 = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        const uint32_t t1 = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off + 4, 0, 0);
+        const float a = __uint_as_float(t0 << 16), b = __uint_as_float(t0 & 0xffff0000u);
+        const float c = __uint_as_float(t1 << 16), d = __uint_as_float(t1 & 0xffff0000u);
+        const float top = fmaf(sx, b - a, a);
+        const float bot = fmaf(sx, d - c, c);
+        return fmaf(sy, bot - top, top);
+    }
+};
+
+// The pair layout reads the same bytes per tap row as the plain layout, but
+// every load is aligned to its own size.
+template <typename T> struct Sampler<T, 2> {
+    static constexpr int kShift = sizeof(T) == 4 ? 3 : 2;
+    static __device__ __forceinline__ float sample(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t row,
+                                                   float sx, float sy)
+    {
+        const float top = Taps<T>::row(r, off, 0, sx);
+        const float bot = Taps<T>::row(r, off, row, sx);
+        return fmaf(sy, bot - top, top);
+    }
+};
+
 // Workgroup -> tile remap: hardware hands consecutive workgroups to the 8
 // XCDs round-robin; this bijection gives XCD j the contiguous tile range
 // [j*q + min(j, r), ...) so its L2 serves one slab of the volume.
@@ -112,9 +195,20 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
     return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + j;
 }
 
+// Thread -> voxel mapping.  A wavefront owns an 8 x 8 patch of (x, y) columns
+// and every lane a strip of S voxels along z.  The 64 voxels of one strip
+// step lie in one plane, so their projections fall onto the same one or two
+// detector rows within a few tens of pixels: each tap load of the wavefront
+// touches only a handful of cache lines.  A workgroup holds NW patches
+// (1 x 1, 2 x 1 or 2 x 2).
+template <int NW> struct Patch {
+    static constexpr int kBX = NW >= 2 ? 2 : 1;
+    static constexpr int kBY = NW / kBX;
+};
+
 struct TilePos {
-    int x, y0, zl;
-    double xd, yd, zd;   // centred voxel indices of the strip start
+    int x, y, z0;          // column and first plane (buffer-local) of the lane's strip
+    double xd, yd, zd;     // centred voxel indices of the strip's anchor voxel
 };
 
 template <int S, int NW>
@@ -127,28 +221,29 @@ __device__ __forceinline__ TilePos tile_pos(const TileArgs& a, int tile)
     const int t2 = tile / a.tiles_x;
     const int ty = t2 % a.tiles_y;
     const int tz = t2 / a.tiles_y;
-    p.x = tx * kWave + lane;
-    p.y0 = ty * S;
-    p.zl = tz * NW + wave;
+    p.x = (tx * Patch<NW>::kBX + wave % Patch<NW>::kBX) * 8 + (lane & 7);
+    p.y = (ty * Patch<NW>::kBY + wave / Patch<NW>::kBX) * 8 + (lane >> 3);
+    p.z0 = tz * S;
     p.xd = (double)(p.x - a.ctr);
-    p.yd = (double)(p.y0 - a.ctr);
-    p.zd = (double)(a.z_begin + p.zl - a.ctr);
+    p.yd = (double)(p.y - a.ctr);
+    p.zd = (double)(a.z_begin + p.z0 + S / 2 - a.ctr);
     return p;
 }
 
-// Per lane and projection: detector coordinates of the strip start in FP64,
-// split into an integer anchor pixel (au, av) and FP32 remainders that are
-// stepped along the strip.  u/w then only has to resolve a few pixels in
-// FP32 instead of the detector half-width, which is what keeps the sampling
-// position accurate to ~1e-5 px at 1248x960.
+// Per lane and projection: detector coordinates of the strip's middle voxel
+// in FP64, split into an integer anchor pixel (au, av) and FP32 remainders
+// that are stepped along the strip.  u/w then only has to resolve a few
+// pixels in FP32 instead of the detector half-width, which is what keeps the
+// sampling position accurate to ~1e-5 px at 1248x960.
 struct Strip {
-    float ub, vb, wb;          // u - au w, v - av w, w at the strip start
-    float du, dv, dw;          // steps per voxel along y
+    float ub, vb, wb;          // u - au w, v - av w, w at the anchor voxel
+    float du, dv, dw;          // steps per voxel along z
+    float fau, fav;            // anchor pixel (au, av), centred detector coordinates
     float lox, hix, loy, hiy;  // clamp range of the remainders (detector border, minus anchor)
     int base;                  // byte offset of the anchor pixel in a staged image
 };
 
-template <int ES>
+template <int SHIFT>
 __device__ __forceinline__ Strip strip_setup(const double* c, const TilePos& p, const TileArgs& a, int wp)
 {
     const double ub = fma(p.xd, c[0], fma(p.yd, c[1], fma(p.zd, c[2], c[3])));
@@ -164,15 +259,35 @@ __device__ __forceinline__ Strip strip_setup(const double* c, const TilePos& p, 
     st.ub = (float)fma(-dau, wb, ub);
     st.vb = (float)fma(-dav, wb, vb);
     st.wb = wf;
-    st.du = (float)fma(-dau, c[9], c[1]);
-    st.dv = (float)fma(-dav, c[9], c[5]);
-    st.dw = (float)c[9];
+    st.du = (float)fma(-dau, c[10], c[2]);
+    st.dv = (float)fma(-dav, c[10], c[6]);
+    st.dw = (float)c[10];
+    st.fau = fau;
+    st.fav = fav;
     st.lox = a.lo_x - fau;
     st.hix = a.hi_x - fau;
     st.loy = a.lo_y - fav;
     st.hiy = a.hi_y - fav;
-    st.base = ((__mul24((int)fav, wp) + (int)fau) << (ES == 4 ? 2 : 1)) + (int)a.centre_bytes;
+    st.base = ((__mul24((int)fav, wp) + (int)fau) << SHIFT) + (int)a.centre_bytes;
     return st;
+}
+
+// Clipping (the paper's clipping mask, per wavefront): does the lane's strip
+// touch the detector?  The strip projects onto the segment between its first
+// and last voxel (w > 0), so if that segment's bounding box misses the
+// support (-1, W) x (-1, H), every tap of every voxel is zero.  A 0.01 px
+// margin keeps the test conservative under FP32 rounding.
+template <int S>
+__device__ __forceinline__ bool strip_touches(const Strip& st)
+{
+    constexpr float t0 = (float)(-(S / 2)), t1 = (float)(S - 1 - S / 2);
+    const float r0 = __builtin_amdgcn_rcpf(fmaf(t0, st.dw, st.wb));
+    const float r1 = __builtin_amdgcn_rcpf(fmaf(t1, st.dw, st.wb));
+    const float x0 = fmaf(t0, st.du, st.ub) * r0, y0 = fmaf(t0, st.dv, st.vb) * r0;
+    const float x1 = fmaf(t1, st.du, st.ub) * r1, y1 = fmaf(t1, st.dv, st.vb) * r1;
+    constexpr float m = 0.99f;   // support edge is border + 1, minus the margin
+    return fmaxf(x0, x1) > st.lox + m && fminf(x0, x1) < st.hix - m &&
+           fmaxf(y0, y1) > st.loy + m && fminf(y0, y1) < st.hiy - m;
 }
 
 // The 12 FP64 coefficients of projection k (16 are stored per projection).
@@ -189,53 +304,71 @@ __device__ __forceinline__ Coef load_coef(const double* tab, int k)
     return r;
 }
 
-// Backprojection of all projections into one tile: 64 x-columns x S y-rows
-// per wavefront, NW wavefronts stacked along z.
-template <typename T, int S, int NW>
+// Backprojection of all projections into one tile: NW patches of 8 x 8
+// columns, S planes deep.
+template <typename T, int LAY, int S, int NW>
 __device__ __forceinline__ void bp_tile(const TileArgs& a, int tile)
 {
-    constexpr int ES = sizeof(T);
+    using Smp = Sampler<T, LAY>;
     const TilePos p = tile_pos<S, NW>(a, tile);
     float acc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = 0.0f;
     const unsigned char* img = a.proj;
     const uint32_t row = a.row_bytes;
-    const int wp = (int)(a.row_bytes / ES);
+    const int wp = (int)(a.row_bytes >> Smp::kShift);
     // coefficients of projection k+1 are fetched while projection k is processed
     Coef next = load_coef(a.coef, 0);
     for (int k = 0; k < a.n_proj; ++k, img += a.proj_stride) {
         const Coef cur = next;
         if (k + 1 < a.n_proj) next = load_coef(a.coef, k + 1);
-        const Strip st = strip_setup<ES>(cur.c, p, a, wp);
+        const Strip st = strip_setup<Smp::kShift>(cur.c, p, a, wp);
+        if (__builtin_amdgcn_ballot_w64(strip_touches<S>(st)) == 0) continue;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const float u = fmaf((float)s, st.du, st.ub);
-            const float v = fmaf((float)s, st.dv, st.vb);
-            const float w = fmaf((float)s, st.dw, st.wb);
+            constexpr int kMid = S / 2;
+            const float t = (float)(s - kMid);
+            const float u = fmaf(t, st.du, st.ub);
+            const float v = fmaf(t, st.dv, st.vb);
+            const float w = fmaf(t, st.dw, st.wb);
             const float r = __builtin_amdgcn_rcpf(w);
             const float dx = __builtin_amdgcn_fmed3f(u * r, st.lox, st.hix);
             const float dy = __builtin_amdgcn_fmed3f(v * r, st.loy, st.hiy);
             const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
-            const uint32_t off = tap_offset<T>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
-            const float top = Taps<T>::row(rs, off, 0, sx);
-            const float bot = Taps<T>::row(rs, off, row, sx);
-            const float val = fmaf(sy, bot - top, top);
+            const uint32_t off = tap_offset<Smp::kShift>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
+            const float val = Smp::sample(rs, off, row, sx, sy);
             acc[s] = fmaf(val, r * r, acc[s]);
         }
     }
-    if (p.x < a.L && p.zl < a.z_count) {
-        float* out = a.vol + ((int64_t)p.zl * a.L + p.y0) * a.L + p.x;
+    if (p.x < a.L && p.y < a.L) {
+        const int64_t plane = (int64_t)a.L * a.L;
+        float* out = a.vol + ((int64_t)p.z0 * a.L + p.y) * a.L + p.x;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            if (p.y0 + s < a.L) {
+            if (p.z0 + s < a.z_count) {
                 float v = acc[s] * a.out_scale;
-                if (a.accumulate) v += out[(int64_t)s * a.L];
-                out[(int64_t)s * a.L] = v;
+                if (a.accumulate) v += out[s * plane];
+                out[s * plane] = v;
             }
         }
     }
+}
+
+template <int LAY, int S, int NW>
+__device__ __forceinline__ void bp_tile_lay(const TileArgs& a, int tile)
+{
+    if (a.dtype == 1) bp_tile<__half, LAY, S, NW>(a, tile);
+    else if (a.dtype == 2) bp_tile<bf16_t, LAY, S, NW>(a, tile);
+    else bp_tile<float, LAY, S, NW>(a, tile);
+}
+
+template <int S, int NW>
+__device__ __forceinline__ void bp_tile_any(const TileArgs& a, int tile)
+{
+    if (a.layout == 1) bp_tile_lay<1, S, NW>(a, tile);
+    else if (a.layout == 2) bp_tile_lay<2, S, NW>(a, tile);
+    else bp_tile_lay<0, S, NW>(a, tile);
 }
 
 // Register budget: longer strips keep more taps in flight, so they are allowed
@@ -243,12 +376,207 @@ __device__ __forceinline__ void bp_tile(const TileArgs& a, int tile)
 template <int S>
 constexpr int waves_per_eu() { return S <= 4 ? 8 : S <= 8 ? 6 : S <= 16 ? 4 : 3; }
 
-template <typename T, int S, int NW>
+template <typename T, int LAY, int S, int NW>
 __global__ __launch_bounds__(kWave * NW)
     __attribute__((amdgpu_waves_per_eu(waves_per_eu<S>(), waves_per_eu<S>()))) void bp_kernel(TileArgs a)
 {
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    bp_tile<T, S, NW>(a, tile);
+    bp_tile<T, LAY, S, NW>(a, tile);
+}
+
+// ----------------------------------------------------------------- LDS tiles
+// Window prepass: for every (tile, projection) the staged-pixel window that
+// holds all taps of the tile's voxels, from the projections of the tile's
+// eight corner voxels in FP64 (w > 0 on the box, so the projected box lies in
+// the hull of its corners), widened by one pixel against FP32 rounding in the
+// kernel.  A tile whose footprint misses the detector gets an empty window:
+// the paper's clipping mask at tile granularity.
+__global__ void window_kernel(TileArgs a, int strip, int bx, int by, Win* __restrict__ out)
+{
+    const int64_t n_tiles = (int64_t)a.tiles_x * a.tiles_y * a.tiles_z;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles * a.n_proj) return;
+    const int tile = (int)(t / a.n_proj), k = (int)(t - (int64_t)tile * a.n_proj);
+    const int tx = tile % a.tiles_x, t2 = tile / a.tiles_x;
+    const int ty = t2 % a.tiles_y, tz = t2 / a.tiles_y;
+    const int x0 = tx * 8 * bx, x1 = min(x0 + 8 * bx, a.L) - 1;
+    const int y0 = ty * 8 * by, y1 = min(y0 + 8 * by, a.L) - 1;
+    const int z0 = tz * strip, z1 = min(z0 + strip, a.z_count) - 1;
+    const double* c = a.coef + 16 * k;
+    double ilo = 1e300, ihi = -1e300, jlo = 1e300, jhi = -1e300;
+    for (int q = 0; q < 8; ++q) {
+        const double X = (double)(((q & 1) ? x1 : x0) - a.ctr);
+        const double Y = (double)(((q & 2) ? y1 : y0) - a.ctr);
+        const double Z = (double)(a.z_begin + ((q & 4) ? z1 : z0) - a.ctr);
+        const double u = c[0] * X + c[1] * Y + c[2] * Z + c[3];
+        const double v = c[4] * X + c[5] * Y + c[6] * Z + c[7];
+        const double w = c[8] * X + c[9] * Y + c[10] * Z + c[11];
+        const double ix = u / w, iy = v / w;
+        ilo = fmin(ilo, ix); ihi = fmax(ihi, ix);
+        jlo = fmin(jlo, iy); jhi = fmax(jhi, iy);
+    }
+    Win wv;
+    // support of a sample, centred coordinates: (-1 - cu, W - cu) = (lo + 1, hi - 1)
+    const bool off = !(ihi > a.lo_x + 0.99 && ilo < a.hi_x - 0.99 && jhi > a.lo_y + 0.99 && jlo < a.hi_y - 0.99);
+    if (off || !(ilo == ilo) || !(jlo == jlo)) {
+        wv.i0 = 1; wv.i1 = 0; wv.j0 = 1; wv.j1 = 0;
+    } else {
+        const double cil = fmin(fmax(floor(ilo) - 1.0, (double)a.lo_x), (double)a.hi_x + 1.0);
+        const double cih = fmin(fmax(floor(ihi) + 2.0, (double)a.lo_x), (double)a.hi_x + 1.0);
+        const double cjl = fmin(fmax(floor(jlo) - 1.0, (double)a.lo_y), (double)a.hi_y + 1.0);
+        const double cjh = fmin(fmax(floor(jhi) + 2.0, (double)a.lo_y), (double)a.hi_y + 1.0);
+        wv.i0 = (int16_t)((int)cil + a.cu + kPadLo);
+        wv.i1 = (int16_t)((int)cih + a.cu + kPadLo);
+        wv.j0 = (int16_t)((int)cjl + a.cv + kPadLo);
+        wv.j1 = (int16_t)((int)cjh + a.cv + kPadLo);
+    }
+    out[t] = wv;
+}
+
+// Staged pixels of one LDS chunk (4 consecutive pixels of a row, 16-byte
+// aligned in the staged image), widened to FP32.
+template <typename T> struct Chunk;
+template <> struct Chunk<float> {
+    static __device__ __forceinline__ float4 load(__amdgpu_buffer_rsrc_t r, uint32_t px)
+    {
+        const uint32_t o = px * 4;
+        return make_float4(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0)),
+                           __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o + 4, 0, 0)),
+                           __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o + 8, 0, 0)),
+                           __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o + 12, 0, 0)));
+    }
+};
+template <> struct Chunk<__half> {
+    static __device__ __forceinline__ float4 load(__amdgpu_buffer_rsrc_t r, uint32_t px)
+    {
+        const uint32_t o = px * 2;
+        const uint32_t a = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o + 4, 0, 0);
+        return make_float4(__half2float(__ushort_as_half((unsigned short)(a & 0xffffu))),
+                           __half2float(__ushort_as_half((unsigned short)(a >> 16))),
+                           __half2float(__ushort_as_half((unsigned short)(b & 0xffffu))),
+                           __half2float(__ushort_as_half((unsigned short)(b >> 16))));
+    }
+};
+template <> struct Chunk<bf16_t> {
+    static __device__ __forceinline__ float4 load(__amdgpu_buffer_rsrc_t r, uint32_t px)
+    {
+        const uint32_t o = px * 2;
+        const uint32_t a = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o + 4, 0, 0);
+        return make_float4(__uint_as_float(a << 16), __uint_as_float(a & 0xffff0000u),
+                           __uint_as_float(b << 16), __uint_as_float(b & 0xffff0000u));
+    }
+};
+
+constexpr int kLdsCap = 8192;   // FP32 pixels of the per-workgroup projection tile (32 KiB)
+
+// Backprojection with the projection footprint of the workgroup staged in
+// LDS: per projection the tile's window is copied from the staged image with
+// aligned 16-byte loads (all threads), and the four taps of every voxel are
+// then read from LDS, which keeps the scattered gathers off the vector-memory
+// path.  A window larger than the LDS tile falls back to gathers from the
+// staged image for that projection.
+// Occupancy of the LDS kernel: five 32 KiB tiles fit in the 160 KiB of a CU.
+template <int S, int NW>
+constexpr int lds_waves_per_eu()
+{
+    return (5 * NW / 4) < 1 ? 1 : ((5 * NW / 4) < waves_per_eu<S>() ? (5 * NW / 4) : waves_per_eu<S>());
+}
+
+template <typename T, int S, int NW>
+__global__ __launch_bounds__(kWave * NW)
+    __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<S, NW>(), lds_waves_per_eu<S, NW>()))) void bp_lds_kernel(TileArgs a)
+{
+    __shared__ __attribute__((aligned(16))) float lds[kLdsCap];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const TilePos p = tile_pos<S, NW>(a, tile);
+    float acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = 0.0f;
+    const unsigned char* img = a.proj;
+    const uint32_t row = a.row_bytes;
+    const int wp = (int)(a.row_bytes / sizeof(T));
+    const Win* wins = a.win + (int64_t)tile * a.n_proj;
+    Coef next = load_coef(a.coef, 0);
+    for (int k = 0; k < a.n_proj; ++k, img += a.proj_stride) {
+        const Coef cur = next;
+        if (k + 1 < a.n_proj) next = load_coef(a.coef, k + 1);
+        const Win wv = wins[k];
+        if (wv.i0 > wv.i1) continue;                        // tile clipped for this projection
+        const int c_lo = wv.i0 & ~3, c_hi = wv.i1 | 3;
+        const int tw = c_hi - c_lo + 1, th = wv.j1 - wv.j0 + 1;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
+        if (tw * th <= kLdsCap) {
+            __syncthreads();                                // previous projection's reads are done
+            const int nc = tw >> 2, total = nc * th;
+            const float inv_nc = 1.0f / (float)nc;
+            for (int e = threadIdx.x; e < total; e += kWave * NW) {
+                const int r = (int)(((float)e + 0.5f) * inv_nc);
+                const int cc = e - r * nc;
+                const float4 v = Chunk<T>::load(rs, (uint32_t)((wv.j0 + r) * wp + c_lo + 4 * cc));
+                *reinterpret_cast<float4*>(&lds[r * tw + 4 * cc]) = v;
+            }
+            __syncthreads();
+            const Strip st = strip_setup<2>(cur.c, p, a, wp);
+            // anchor in staged-pixel coordinates; clamp so both tap columns
+            // and rows stay inside the window held in LDS
+            const float ax = st.fau + (float)(a.cu + kPadLo), ay = st.fav + (float)(a.cv + kPadLo);
+            const float lox = (float)c_lo - ax, hix = (float)(c_hi - 1) - ax;
+            const float loy = (float)wv.j0 - ay, hiy = (float)(wv.j1 - 1) - ay;
+            const int base = (((int)ay - wv.j0) * tw + ((int)ax - c_lo)) * 4;
+            const uint32_t row_l = (uint32_t)tw * 4;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                constexpr int kMid = S / 2;
+                const float t = (float)(s - kMid);
+                const float u = fmaf(t, st.du, st.ub);
+                const float v = fmaf(t, st.dv, st.vb);
+                const float w = fmaf(t, st.dw, st.wb);
+                const float r = __builtin_amdgcn_rcpf(w);
+                const float dx = __builtin_amdgcn_fmed3f(u * r, lox, hix);
+                const float dy = __builtin_amdgcn_fmed3f(v * r, loy, hiy);
+                const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
+                const uint32_t off = tap_offset<2>(cvt_floor(dx), cvt_floor(dy), tw, base);
+                const float* q0 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off);
+                const float* q1 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off + row_l);
+                const float top = fmaf(sx, q0[1] - q0[0], q0[0]);
+                const float bot = fmaf(sx, q1[1] - q1[0], q1[0]);
+                const float val = fmaf(sy, bot - top, top);
+                acc[s] = fmaf(val, r * r, acc[s]);
+            }
+        } else {
+            // window larger than the LDS tile: gather from the staged image
+            const Strip st = strip_setup<Sampler<T, 0>::kShift>(cur.c, p, a, wp);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                constexpr int kMid = S / 2;
+                const float t = (float)(s - kMid);
+                const float u = fmaf(t, st.du, st.ub);
+                const float v = fmaf(t, st.dv, st.vb);
+                const float w = fmaf(t, st.dw, st.wb);
+                const float r = __builtin_amdgcn_rcpf(w);
+                const float dx = __builtin_amdgcn_fmed3f(u * r, st.lox, st.hix);
+                const float dy = __builtin_amdgcn_fmed3f(v * r, st.loy, st.hiy);
+                const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
+                const uint32_t off = tap_offset<Sampler<T, 0>::kShift>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
+                const float val = Sampler<T, 0>::sample(rs, off, row, sx, sy);
+                acc[s] = fmaf(val, r * r, acc[s]);
+            }
+        }
+    }
+    if (p.x < a.L && p.y < a.L) {
+        const int64_t plane = (int64_t)a.L * a.L;
+        float* out = a.vol + ((int64_t)p.z0 * a.L + p.y) * a.L + p.x;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (p.z0 + s < a.z_count) {
+                float v = acc[s] * a.out_scale;
+                if (a.accumulate) v += out[s * plane];
+                out[s * plane] = v;
+            }
+        }
+    }
 }
 
 // Persistent backprojection over many scans: every workgroup pulls
@@ -276,12 +604,7 @@ __global__ __launch_bounds__(kWave * NW)
         }
         const TileArgs a = scans[lo];
         const int tile = item - item_begin[lo];
-        if (a.dtype == 1)
-            bp_tile<__half, S, NW>(a, tile);
-        else if (a.dtype == 2)
-            bp_tile<bf16_t, S, NW>(a, tile);
-        else
-            bp_tile<float, S, NW>(a, tile);
+        bp_tile_any<S, NW>(a, tile);
     }
 }
 
@@ -296,11 +619,12 @@ __global__ __launch_bounds__(kWave * NW)
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const TilePos p = tile_pos<S, NW>(a, tile);
     float xv[S];
-    const bool col_ok = p.x < a.L && p.zl < a.z_count;
-    const float* in = a.vol + ((int64_t)p.zl * a.L + p.y0) * a.L + p.x;
+    const bool col_ok = p.x < a.L && p.y < a.L;
+    const int64_t plane = (int64_t)a.L * a.L;
+    const float* in = a.vol + ((int64_t)p.z0 * a.L + p.y) * a.L + p.x;
 #pragma unroll
     for (int s = 0; s < S; ++s)
-        xv[s] = (col_ok && p.y0 + s < a.L) ? in[(int64_t)s * a.L] * a.out_scale : 0.0f;
+        xv[s] = (col_ok && p.z0 + s < a.z_count) ? in[s * plane] * a.out_scale : 0.0f;
     const unsigned char* img = a.proj;
     const int row = (int)a.row_bytes;
     const int wp = row / 4;
@@ -308,7 +632,8 @@ __global__ __launch_bounds__(kWave * NW)
     for (int k = 0; k < a.n_proj; ++k, img += a.proj_stride) {
         const Coef cur = next;
         if (k + 1 < a.n_proj) next = load_coef(a.coef, k + 1);
-        const Strip st = strip_setup<4>(cur.c, p, a, wp);
+        const Strip st = strip_setup<2>(cur.c, p, a, wp);
+        if (__builtin_amdgcn_ballot_w64(strip_touches<S>(st)) == 0) continue;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
         // a sample touches the detector iff the remainder lies strictly inside
         // (border + 1) on both axes
@@ -316,15 +641,17 @@ __global__ __launch_bounds__(kWave * NW)
         const float in_loy = st.loy + 1.0f, in_hiy = st.hiy - 1.0f;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const float u = fmaf((float)s, st.du, st.ub);
-            const float v = fmaf((float)s, st.dv, st.vb);
-            const float w = fmaf((float)s, st.dw, st.wb);
+            constexpr int kMid = S / 2;
+            const float t = (float)(s - kMid);
+            const float u = fmaf(t, st.du, st.ub);
+            const float v = fmaf(t, st.dv, st.vb);
+            const float w = fmaf(t, st.dw, st.wb);
             const float r = __builtin_amdgcn_rcpf(w);
             const float dx = u * r, dy = v * r;
             const bool hit = dx > in_lox && dx < in_hix && dy > in_loy && dy < in_hiy;
             if (hit && xv[s] != 0.0f) {
                 const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
-                const int off = (int)tap_offset<float>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
+                const int off = (int)tap_offset<2>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
                 const float val = xv[s] * (r * r);
                 const float b = val * sy, t = val - b;   // row weights times value
                 __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(t - t * sx, rs, off, 0, 0);
@@ -337,12 +664,56 @@ __global__ __launch_bounds__(kWave * NW)
 }
 
 // ----------------------------------------------------------------- staging
+// One padded row of the staged layout.  Pixel (ip, jp) of the padded image
+// is the detector pixel (ip - 2, jp - 2), zero outside the detector; the quad
+// layout stores the 2x2 block starting at (ip, jp) instead of one pixel.
+template <typename E>
+__device__ __forceinline__ E padded_px(const E* img, const StageArgs& a, int ip, int jp)
+{
+    const int i = ip - kPadLo, j = jp - kPadLo;
+    return (i >= 0 && i < a.W && j >= 0 && j < a.H) ? img[(int64_t)j * a.W + i] : E(0);
+}
+
 __device__ __forceinline__ void stage_row(const StageArgs& a, int64_t local_row)
 {
     const int k = (int)(local_row / a.Hp);
     const int jp = (int)(local_row - (int64_t)k * a.Hp);
     const int j = jp - kPadLo;
     const bool row_in = j >= 0 && j < a.H;
+    if (a.layout == 1) {
+        if (a.esize == 4) {
+            const float* img = (const float*)a.src + (int64_t)k * a.H * a.W;
+            float4* d = (float4*)(a.dst + (uint64_t)k * a.proj_stride + (uint64_t)jp * a.Wp * 16);
+            for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x)
+                d[ip] = make_float4(padded_px(img, a, ip, jp), padded_px(img, a, ip + 1, jp),
+                                    padded_px(img, a, ip, jp + 1), padded_px(img, a, ip + 1, jp + 1));
+        } else {
+            const unsigned short* img = (const unsigned short*)a.src + (int64_t)k * a.H * a.W;
+            uint2* d = (uint2*)(a.dst + (uint64_t)k * a.proj_stride + (uint64_t)jp * a.Wp * 8);
+            for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x) {
+                const uint32_t t0 = (uint32_t)padded_px(img, a, ip, jp) |
+                                    ((uint32_t)padded_px(img, a, ip + 1, jp) << 16);
+                const uint32_t t1 = (uint32_t)padded_px(img, a, ip, jp + 1) |
+                                    ((uint32_t)padded_px(img, a, ip + 1, jp + 1) << 16);
+                d[ip] = make_uint2(t0, t1);
+            }
+        }
+        return;
+    }
+    if (a.layout == 2) {
+        if (a.esize == 4) {
+            const float* img = (const float*)a.src + (int64_t)k * a.H * a.W;
+            float2* d = (float2*)(a.dst + (uint64_t)k * a.proj_stride + (uint64_t)jp * a.Wp * 8);
+            for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x)
+                d[ip] = make_float2(padded_px(img, a, ip, jp), padded_px(img, a, ip + 1, jp));
+        } else {
+            const unsigned short* img = (const unsigned short*)a.src + (int64_t)k * a.H * a.W;
+            uint32_t* d = (uint32_t*)(a.dst + (uint64_t)k * a.proj_stride + (uint64_t)jp * a.Wp * 4);
+            for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x)
+                d[ip] = (uint32_t)padded_px(img, a, ip, jp) | ((uint32_t)padded_px(img, a, ip + 1, jp) << 16);
+        }
+        return;
+    }
     unsigned char* drow = a.dst + (uint64_t)k * a.proj_stride + (uint64_t)jp * a.Wp * a.esize;
     if (a.esize == 4) {
         const float* src = (const float*)a.src + ((int64_t)k * a.H + (row_in ? j : 0)) * a.W;
@@ -494,16 +865,36 @@ __global__ void zero_u32_kernel(unsigned* p, int n)
 }
 
 // ----------------------------------------------------------------- dispatch
+template <int LAY, int S, int NW>
+void bp_dispatch_q(const TileArgs& a, dim3 grid, dim3 block, hipStream_t st)
+{
+    if (a.dtype == 1)
+        hipLaunchKernelGGL((bp_kernel<__half, LAY, S, NW>), grid, block, 0, st, a);
+    else if (a.dtype == 2)
+        hipLaunchKernelGGL((bp_kernel<bf16_t, LAY, S, NW>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((bp_kernel<float, LAY, S, NW>), grid, block, 0, st, a);
+}
+
 template <int S, int NW>
 hipError_t bp_dispatch_t(const TileArgs& a, int nblocks, hipStream_t st)
 {
     dim3 grid(nblocks), block(kWave * NW);
-    if (a.dtype == 1)
-        hipLaunchKernelGGL((bp_kernel<__half, S, NW>), grid, block, 0, st, a);
-    else if (a.dtype == 2)
-        hipLaunchKernelGGL((bp_kernel<bf16_t, S, NW>), grid, block, 0, st, a);
+    if (a.layout == 3) {
+        if (a.dtype == 1)
+            hipLaunchKernelGGL((bp_lds_kernel<__half, S, NW>), grid, block, 0, st, a);
+        else if (a.dtype == 2)
+            hipLaunchKernelGGL((bp_lds_kernel<bf16_t, S, NW>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((bp_lds_kernel<float, S, NW>), grid, block, 0, st, a);
+        return hipGetLastError();
+    }
+    if (a.layout == 1)
+        bp_dispatch_q<1, S, NW>(a, grid, block, st);
+    else if (a.layout == 2)
+        bp_dispatch_q<2, S, NW>(a, grid, block, st);
     else
-        hipLaunchKernelGGL((bp_kernel<float, S, NW>), grid, block, 0, st, a);
+        bp_dispatch_q<0, S, NW>(a, grid, block, st);
     return hipGetLastError();
 }
 
@@ -584,6 +975,16 @@ int batched_blocks_per_cu(int strip, int waves)
     FDK_TILE_TABLE(X)
 #undef X
     return 0;
+}
+
+hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, hipStream_t s)
+{
+    const int bx = waves >= 2 ? 2 : 1, by = waves / bx;
+    const int64_t n = (int64_t)a.tiles_x * a.tiles_y * a.tiles_z * a.n_proj;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(window_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, strip, bx, by, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_stage(const StageArgs& a, hipStream_t s)

@@ -146,27 +146,29 @@ def test_batched_reports_failing_scan(fdk):
 
 def test_tiles_and_tuning_file(fdk, tmp_path):
     vol = fdk.Volume(512, 0.5)
-    fdk.set_tile(fdk.F16, 4, 1)
-    assert fdk.get_tile(vol, fdk.F16) == (4, 1)
+    fdk.set_tile(fdk.F16, 4, 1, 1)
+    assert fdk.get_tile(vol, fdk.F16) == (4, 1, 1)
     fdk.set_tile(fdk.F16, 0, 0)
     with pytest.raises(fdk.FdkError):
         fdk.set_tile(fdk.F32, 3, 1)
+    with pytest.raises(fdk.FdkError):
+        fdk.set_tile(fdk.F32, 4, 1, 4)
     f = tmp_path / "tune.txt"
-    f.write_text("fdk-tuning 1 gfx950\n# dtype class strip waves\n0 9 8 1\n1 9 2 2\n")
+    f.write_text("fdk-tuning 1 gfx950\n# dtype class strip waves layout\n0 9 8 1 0\n1 9 2 2 1\n")
     assert fdk.load_tuning(str(f)) == 2
-    assert fdk.get_tile(vol, fdk.F32) == (8, 1)
-    assert fdk.get_tile(vol, fdk.F16) == (2, 2)
+    assert fdk.get_tile(vol, fdk.F32) == (8, 1, 0)
+    assert fdk.get_tile(vol, fdk.F16) == (2, 2, 1)
     stale = tmp_path / "stale.txt"
-    stale.write_text("fdk-tuning 0 gfx942\n0 9 4 4\n")
+    stale.write_text("fdk-tuning 0 gfx942\n0 9 4 4 0\n")
     with pytest.raises(fdk.FdkError):
         fdk.load_tuning(str(stale))
-    assert fdk.get_tile(vol, fdk.F32) == (8, 1)   # stale file ignored
+    assert fdk.get_tile(vol, fdk.F32) == (8, 1, 0)   # stale file ignored
     bad = tmp_path / "bad.txt"
-    bad.write_text("fdk-tuning 1 gfx950\n0 9 5 1\n")
+    bad.write_text("fdk-tuning 1 gfx950\n0 9 5 1 0\n")
     with pytest.raises(fdk.FdkError):
         fdk.load_tuning(str(bad))
-    fdk.set_tuning_entry(0, 9, 16, 2)
-    assert fdk.get_tile(vol, fdk.F32) == (16, 2)
+    fdk.set_tuning_entry(0, 9, 16, 2, 1)
+    assert fdk.get_tile(vol, fdk.F32) == (16, 2, 1)
     for dt in (0, 1):
         fdk.set_tuning_entry(dt, 9, 0, 0)   # restore the built-in choice
     assert fdk.get_tile(vol, fdk.F32) == fdk.get_tile(vol, fdk.F32)

@@ -39,18 +39,21 @@ def test_c0_fp32_full_volume(fdk, c0):
     print(f"C0 128^3x124 fp32 rel L2 {err:.3e} PSNR {oracle.psnr(out.cpu().numpy(), ref):.1f} dB")
 
 
+@pytest.mark.parametrize("layout", [0, 1, 2, 3])
 @pytest.mark.parametrize("strip,waves", [(2, 1), (2, 4), (4, 1), (4, 2), (8, 1), (8, 4),
-                                         (16, 1), (16, 2), (16, 4), (2, 2), (4, 4), (8, 2)])
-def test_every_tile_shape_ragged(fdk, strip, waves):
-    """L = 37 (ragged in x, y and z for every shape), odd detector 101 x 77."""
+                                         (16, 1), (16, 2), (16, 4), (2, 2), (4, 4), (8, 2),
+                                         (32, 1), (32, 2), (32, 4)])
+def test_every_tile_shape_ragged(fdk, strip, waves, layout):
+    """L = 37 (ragged in x, y and z for every shape), odd detector 101 x 77,
+    both staged layouts."""
     carm = small_carm(9, 101, 77)
     mats, q = S.filtered_projections(carm, 3)
     L, voxel = 37, 4.0
     geom = fdk.Geometry(mats, carm.width, carm.height)
     vol = fdk.Volume(L, voxel)
-    fdk.set_tile(fdk.F32, strip, waves)
+    fdk.set_tile(fdk.F32, strip, waves, layout)
     try:
-        assert fdk.get_tile(vol, fdk.F32) == (strip, waves)
+        assert fdk.get_tile(vol, fdk.F32) == (strip, waves, layout)
         out = fdk.backproject(q.to(DEV), geom, vol)
         torch.cuda.synchronize()
     finally:
@@ -94,8 +97,9 @@ def test_accumulate_and_slabs(fdk):
     ref = oracle.backproject(L, voxel, mats, q.numpy())
     assert_parity(full.cpu().numpy(), ref, what="full")
     assert_parity(acc.cpu().numpy(), ref + init.cpu().numpy().astype(np.float64), what="accumulate")
-    # a slab computes exactly what the full launch computes for its planes
-    assert torch.equal(slabbed, full)
+    # a slab computes its planes as the full launch does (strips may group the
+    # planes differently, so only FP32 rounding may differ)
+    assert oracle.rel_l2(slabbed.cpu().numpy(), full.cpu().numpy()) < 1e-6
 
 
 def test_projection_subsets_add_up(fdk):

@@ -46,11 +46,14 @@ def test_batched_matches_single_and_oracle(fdk):
     dts = [torch.float32, torch.float16, torch.float32, torch.bfloat16, torch.float32]
     scans, host = make_scans(fdk, SPECS, dts)
     # the batched launch uses one tile shape for all scans; pin it for the single calls
-    s, w = fdk.get_tile(fdk.Volume(max(sp[0] for sp in SPECS), 1.0), fdk.F32)
+    maxvol = fdk.Volume(max(sp[0] for sp in SPECS), 1.0)
+    s, w, _ = fdk.get_tile(maxvol, fdk.F32)
+    # the persistent kernel gathers from staged images (LDS tiles, layout 3, map to layout 0)
+    lays = {dt: (lambda l: 0 if l == 3 else l)(fdk.get_tile(maxvol, dt)[2]) for dt in (fdk.F32, fdk.F16, fdk.BF16)}
     fdk.backproject_batched(scans)
     torch.cuda.synchronize()
     for dt in (fdk.F32, fdk.F16, fdk.BF16):
-        fdk.set_tile(dt, s, w)
+        fdk.set_tile(dt, s, w, lays[dt])
     try:
         for sc, (L, voxel, mats, q, qd, scale) in zip(scans, host):
             single = fdk.backproject(sc.proj, sc.geom, sc.vol, scale=sc.scale)

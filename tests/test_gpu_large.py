@@ -60,7 +60,7 @@ def test_512_fp32_sampled(fdk, c1):
 
 def test_512_fp32_full_planes(fdk, c1):
     """Whole planes: plane 7 lies outside the cone for every projection (all
-    zero), plane 80 is partly clipped, plane 300 crosses the clipped corners."""
+    zero); planes 150 and 300 cross the corners clipped by the fan."""
     carm, mats, q, q64 = c1
     L, voxel = 512, 0.5
     out = fdk.backproject(q, fdk.Geometry(mats, carm.width, carm.height), fdk.Volume(L, voxel))
@@ -68,9 +68,10 @@ def test_512_fp32_full_planes(fdk, c1):
     ref7 = oracle.backproject(L, voxel, mats, q64, z_range=(7, 1))[0]
     assert np.all(ref7 == 0.0)
     assert torch.count_nonzero(out[7]).item() == 0
-    for z in (80, 300):
+    for z in (150, 300):
         ref = oracle.backproject(L, voxel, mats, q64, z_range=(z, 1))[0]
         got = out[z].double().cpu().numpy()
+        assert np.linalg.norm(ref) > 0
         err = oracle.rel_l2(got, ref)
         print(f"512^3 plane {z}: rel L2 {err:.3e}")
         assert err <= REL_L2_FP32
@@ -111,4 +112,6 @@ def test_1024_slabs_sampled(fdk, c1):
     whole = fdk.backproject(q, geom, base)
     torch.cuda.synchronize()
     idx = torch.as_tensor(xyz.astype(np.int64), device=DEV)
-    assert torch.equal(whole[idx[:, 2], idx[:, 1], idx[:, 0]], out[idx[:, 2], idx[:, 1], idx[:, 0]])
+    a = whole[idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    b = out[idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    assert oracle.rel_l2(b, a) < 1e-6
