@@ -64,6 +64,9 @@ typedef enum fdk_dtype {
     FDK_BF16 = 2   /* bfloat16 */
 } fdk_dtype;
 
+/* Tuning slot of the forward projector (fdk_set_tile and the tuning table). */
+#define FDK_TUNE_ADJOINT 3
+
 /* The volume grid (paper: edge L, voxel pitch MM, origin O).  The buffer
  * passed with it holds the planes [z_begin, z_begin + z_count), which lets a
  * large volume be processed as z-slabs. */
@@ -126,8 +129,11 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj,
  *   proj_out   DEVICE, n_proj * height * width float32, written (or added to)
  *   accumulate 0: overwrite, 1: add
  *   stream     hipStream_t or NULL
- * Accumulation uses float atomics: the result is deterministic only up to
- * FP32 rounding order.
+ * With the default tiling each detector pixel is summed in FP64 in LDS and
+ * rounded to FP32 once; the order of the FP64 additions varies from run to
+ * run, so results are reproducible to FP64 rounding before that final
+ * rounding.  Layout 0 accumulates with FP32 atomics in global memory.
+ * FDK_E_GEOMETRY as for fdk_backproject.
  */
 fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume,
                               const fdk_projections* geom, float* proj_out,
@@ -167,7 +173,16 @@ fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width,
  * projection as a zero-bordered image; layout 1 stores with every staged
  * pixel its whole 2x2 bilinear block (four times the staging memory, one load
  * per sample); layout 2 stores with every pixel its right neighbour (twice the
- * memory, aligned row loads).
+ * memory, aligned row loads); layout 3 copies each workgroup's projection
+ * window into LDS and reads the taps there.  The `dtype` argument selects a
+ * tuning slot: FDK_F32, FDK_F16, FDK_BF16 (backprojection by projection
+ * dtype) or FDK_TUNE_ADJOINT (the forward projector).  For the forward
+ * projector, layout 4 (the default) gives each workgroup a detector tile of
+ * `strip` rows (1 <= strip, strip * waves <= 20480) by
+ * min(width, 20480 / (strip * waves)) pixels in `waves` projections
+ * (1, 2, 4 or 8), accumulated in FP64 in LDS and written once; layout 0 scatters
+ * every voxel straight to global memory with float atomics (tile shapes as for
+ * the backprojection).
  * fdk_set_tile pins the choice for a dtype (strip = waves = 0 restores the
  * automatic choice from the tuning table); fdk_get_tile reports what a call
  * with this grid and dtype would use. */

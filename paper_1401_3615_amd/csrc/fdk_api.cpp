@@ -216,9 +216,13 @@ struct ProfScope {
 // ------------------------------------------------------------------ tiles
 struct TileShape { int strip, waves, layout; };
 
+// Tuning slots: FDK_F32, FDK_F16, FDK_BF16 for the backprojection, and one for
+// the adjoint (forward projection).
+constexpr int kAdjointSlot = 3;
+
 struct Tuning {
     std::map<std::pair<int, int>, TileShape> table;  // (dtype, size class) -> shape
-    TileShape forced[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    TileShape forced[4] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // index 3: adjoint
     bool env_loaded = false;
 };
 
@@ -233,6 +237,14 @@ int size_class(int L)
 // workgroup and the longest strip (fewer per-projection set-ups per voxel)
 // that still gives ~4 workgroups per CU on a 256-CU device; FP32 stages the
 // tile footprint in LDS, FP16/BF16 gather whole 2x2 blocks (8 bytes) per load.
+// The adjoint (tuning slot 3) privatises its detector window in LDS; bigger
+// workgroups (16 patches, 32 x 32 columns) pre-sum more voxels per pixel
+// before the global atomics.
+TileShape default_adjoint_tile(int)
+{
+    return {16, 1, 4};   // detector tiles of 16 rows, one projection per workgroup
+}
+
 TileShape default_tile(int L, int dtype)
 {
     const int layout = dtype == FDK_F32 ? 3 : 1;
@@ -424,7 +436,16 @@ TileShape pick_tile(int L, int dtype)
     if (f.strip > 0) return f;
     auto it = g_tune.table.find({dtype, size_class(L)});
     if (it != g_tune.table.end()) return it->second;
-    return default_tile(L, dtype);
+    return dtype == kAdjointSlot ? default_adjoint_tile(L) : default_tile(L, dtype);
+}
+
+bool valid_shape(int slot, TileShape t)
+{
+    if (slot == kAdjointSlot) {
+        if (t.layout == 4) return t.strip >= 1 && t.strip * t.waves <= kBandCap && supported_band_group(t.waves);
+        return t.layout == 0 && supported_tile(t.strip, t.waves) != 0;
+    }
+    return t.layout >= 0 && t.layout <= 3 && supported_tile(t.strip, t.waves) != 0;
 }
 
 void load_env_tuning();
@@ -461,7 +482,7 @@ TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, Til
     a.out_scale = out_scale;
     a.accumulate = accumulate ? 1 : 0;
     // a workgroup covers (8 bx) x (8 by) columns and `strip` planes
-    const int bx = t.waves >= 2 ? 2 : 1, by = t.waves / bx;
+    const int bx = t.waves >= 16 ? 4 : t.waves >= 2 ? 2 : 1, by = t.waves / bx;
     a.tiles_x = (v->L + 8 * bx - 1) / (8 * bx);
     a.tiles_y = (v->L + 8 * by - 1) / (8 * by);
     a.tiles_z = (v->z_count + t.strip - 1) / t.strip;
@@ -596,6 +617,54 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     return end_call(*d, s);
 }
 
+// Forward projection by detector-tile ownership: each workgroup owns t.strip
+// detector rows (as many columns as fit its LDS) of t.waves projections and
+// writes them once, straight into the caller's stack.
+static fdk_status forwardproject_tiles(const fdk_volume* vol, const float* volume, const fdk_projections* geom,
+                                float* proj_out, int accumulate, void* stream, TileShape t)
+{
+    fdk_status st;
+    BandArgs b{};
+    b.th = std::min(t.strip, geom->height);
+    b.tw = std::min(geom->width, kBandCap / (b.th * t.waves));
+    b.tiles_u = (geom->width + b.tw - 1) / b.tw;
+    b.tiles_v = (geom->height + b.th - 1) / b.th;
+    if ((int64_t)b.tiles_u * b.tiles_v * ((geom->n_proj + t.waves - 1) / t.waves) > 0x7fffffffLL)
+        return fail(FDK_E_INVALID_ARG, "detector tile grid too large");
+    DeviceState* d = nullptr;
+    if ((st = device_state(&d)) != FDK_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = begin_call(*d, s)) != FDK_OK) return st;
+    hipError_t e = ensure(d->coef_dev, (size_t)geom->n_proj * 16 * sizeof(double));
+    if (e != hipSuccess) return fail(FDK_E_NOMEM, "coefficient workspace: %s", hipGetErrorString(e));
+    const double* coef64 = nullptr;
+    float out_scale = 1.0f;
+    if ((st = coef_table(*d, vol, geom, s, &coef64, &out_scale)) != FDK_OK) return st;
+    {
+        ProfScope ps("fold", s);
+        HIP_TRY(launch_fold_single(coef64, nullptr, static_cast<double*>(d->coef_dev.p), geom->n_proj, s));
+    }
+    b.coef = static_cast<const double*>(d->coef_dev.p);
+    b.vol = volume;
+    b.out = proj_out;
+    b.n_proj = geom->n_proj;
+    b.L = vol->L;
+    b.z_begin = vol->z_begin;
+    b.z_count = vol->z_count;
+    b.ctr = vol->L / 2;
+    b.W = geom->width;
+    b.H = geom->height;
+    b.cu = geom->width / 2;
+    b.cv = geom->height / 2;
+    b.out_scale = out_scale;
+    b.accumulate = accumulate;
+    {
+        ProfScope ps("fp", s);
+        HIP_TRY(launch_fp_band(b, t.waves, s));
+    }
+    return end_call(*d, s);
+}
+
 fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const fdk_projections* geom,
                               float* proj_out, int accumulate, void* stream)
 {
@@ -605,8 +674,8 @@ fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const 
     if (proj_out == nullptr) return fail(FDK_E_INVALID_ARG, "projection output is NULL");
     std::lock_guard<std::mutex> lock(g_mu);
     load_env_tuning();
-    TileShape t = pick_tile(vol->L, FDK_F32);
-    t.layout = 0;   // the adjoint accumulates into a plain zero-bordered image
+    const TileShape t = pick_tile(vol->L, kAdjointSlot);
+    if (t.layout == 4) return forwardproject_tiles(vol, volume, geom, proj_out, accumulate, stream, t);
     TileArgs probe = make_args(vol, geom, 4, t, nullptr, nullptr, nullptr, 1.0f, 0, FDK_F32);
     if ((st = check_grid(probe)) != FDK_OK) return st;
 
@@ -869,15 +938,16 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
 fdk_status fdk_set_tile(int32_t dtype, int32_t strip, int32_t waves, int32_t layout)
 {
     g_last_error.clear();
-    if (dtype < 0 || dtype > 2) return fail(FDK_E_UNSUPPORTED, "unknown dtype %d", dtype);
+    if (dtype < 0 || dtype > kAdjointSlot) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
     std::lock_guard<std::mutex> lock(g_mu);
     if (strip == 0 && waves == 0) {
         g_tune.forced[dtype] = {0, 0, 0};
         return FDK_OK;
     }
-    if (!supported_tile(strip, waves)) return fail(FDK_E_INVALID_ARG, "tile %dx%d not compiled", strip, waves);
-    if (layout < 0 || layout > 3) return fail(FDK_E_INVALID_ARG, "layout %d", layout);
-    g_tune.forced[dtype] = {strip, waves, layout};
+    const TileShape t{strip, waves, layout};
+    if (!valid_shape(dtype, t))
+        return fail(FDK_E_INVALID_ARG, "tile %dx%d layout %d not compiled for slot %d", strip, waves, layout, dtype);
+    g_tune.forced[dtype] = t;
     return FDK_OK;
 }
 
@@ -887,7 +957,7 @@ fdk_status fdk_get_tile(const fdk_volume* vol, int32_t dtype, int32_t* strip, in
     g_last_error.clear();
     fdk_status st = check_volume(vol);
     if (st != FDK_OK) return st;
-    if (dtype < 0 || dtype > 2) return fail(FDK_E_UNSUPPORTED, "unknown dtype %d", dtype);
+    if (dtype < 0 || dtype > kAdjointSlot) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
     if (strip == nullptr || waves == nullptr || layout == nullptr) return fail(FDK_E_INVALID_ARG, "NULL output");
     std::lock_guard<std::mutex> lock(g_mu);
     load_env_tuning();
@@ -902,16 +972,17 @@ fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip
                                 int32_t layout)
 {
     g_last_error.clear();
-    if (dtype < 0 || dtype > 2) return fail(FDK_E_UNSUPPORTED, "unknown dtype %d", dtype);
+    if (dtype < 0 || dtype > kAdjointSlot) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
     if (size_class < 0 || size_class > 15) return fail(FDK_E_INVALID_ARG, "size class %d", size_class);
     std::lock_guard<std::mutex> lock(g_mu);
     if (strip == 0 && waves == 0) {
         g_tune.table.erase({dtype, size_class});
         return FDK_OK;
     }
-    if (!supported_tile(strip, waves)) return fail(FDK_E_INVALID_ARG, "tile %dx%d not compiled", strip, waves);
-    if (layout < 0 || layout > 3) return fail(FDK_E_INVALID_ARG, "layout %d", layout);
-    g_tune.table[{dtype, size_class}] = {strip, waves, layout};
+    const TileShape t{strip, waves, layout};
+    if (!valid_shape(dtype, t))
+        return fail(FDK_E_INVALID_ARG, "tile %dx%d layout %d not compiled for slot %d", strip, waves, layout, dtype);
+    g_tune.table[{dtype, size_class}] = t;
     return FDK_OK;
 }
 
@@ -942,7 +1013,7 @@ int32_t fdk_load_tuning(const char* path)
         }
         int dt, cls, s, w, lay;
         if (std::sscanf(line, "%d %d %d %d %d", &dt, &cls, &s, &w, &lay) == 5) {
-            if (dt < 0 || dt > 2 || cls < 0 || cls > 15 || !supported_tile(s, w) || lay < 0 || lay > 3) {
+            if (dt < 0 || dt > kAdjointSlot || cls < 0 || cls > 15 || !valid_shape(dt, TileShape{s, w, lay})) {
                 std::fclose(f);
                 return fail(FDK_E_INVALID_ARG, "%s: bad entry '%d %d %d %d %d'", path, dt, cls, s, w, lay);
             }

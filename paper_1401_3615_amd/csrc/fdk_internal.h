@@ -50,6 +50,25 @@ struct TileArgs {
     int32_t cu, cv;              // integer detector centre (W/2, H/2)
 };
 
+// Forward projection by detector-tile ownership: one workgroup per
+// (detector tile, group of projections) accumulates every voxel's
+// contribution to its tiles in LDS and writes them once.
+struct BandArgs {
+    const double* coef;          // n_proj x 16 doubles (centred composition, power-of-two scaled)
+    const float* vol;            // planes z_begin .. z_begin + z_count
+    float* out;                  // n_proj x H x W
+    int32_t n_proj, L, z_begin, z_count, ctr;
+    int32_t W, H, cu, cv;
+    int32_t tw, th, tiles_u, tiles_v;
+    float out_scale;
+    int32_t accumulate;
+};
+
+// group = projections per workgroup (1, 2, 4 or 8); P tw th <= kBandCap
+hipError_t launch_fp_band(const BandArgs& b, int group, hipStream_t s);
+int supported_band_group(int group);
+constexpr int kBandCap = 20480;   // FP64 accumulators of one workgroup's detector tiles (160 KiB of LDS)
+
 // One projection stack to stage into the padded layout.
 struct StageArgs {
     const void* src;             // [n][H][W] elements of esize bytes

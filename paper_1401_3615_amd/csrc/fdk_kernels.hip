@@ -202,7 +202,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks)
 // touches only a handful of cache lines.  A workgroup holds NW patches
 // (1 x 1, 2 x 1 or 2 x 2).
 template <int NW> struct Patch {
-    static constexpr int kBX = NW >= 2 ? 2 : 1;
+    static constexpr int kBX = NW >= 16 ? 4 : NW >= 2 ? 2 : 1;
     static constexpr int kBY = NW / kBX;
 };
 
@@ -663,6 +663,191 @@ __global__ __launch_bounds__(kWave * NW)
     }
 }
 
+// ----------------------------------------------------------------- adjoint by detector tiles
+// The forward projector as a gather over detector tiles: workgroup (tile, g)
+// owns the pixels [i0, i1) x [j0, j1) of the P projections g P .. g P + P - 1,
+// one FP64 LDS accumulation tile each, and writes them once: no global
+// atomics.  (LDS FP64 adds also run about ten times faster than FP32 ones.)
+// Its threads walk the (x, y) voxel columns.  Along a column u/w and v/w are
+// monotonic in z (w > 0 on the processed planes), so the planes whose samples
+// can put a tap into the tile's rows form one interval per projection, found
+// from the column's two end planes and the crossing planes in closed form;
+// a column whose u/w range over that interval misses the tile's columns is
+// skipped for that projection.  Each voxel value in the union of the P
+// intervals is read once and scattered into all P tiles: value/w^2 times each
+// bilinear weight, for the taps that fall inside the tile, sampled exactly as
+// the backprojection samples (FP64 anchor at the interval's middle plane,
+// FP32 remainders).  The interval test runs in FP32 with a 0.05 px margin,
+// which far exceeds its rounding error, so it can only admit planes that add
+// nothing, never drop one that adds something.
+constexpr int kBandThreads = 1024;
+constexpr float kBandMargin = 0.05f;
+
+struct BandCol {
+    float za, zb;   // plane interval (centred), za > zb if empty
+};
+
+// Planes z in [zlo, zhi] (centred indices) whose sample can have a tap in the
+// detector rows/columns [tlo, thi) x [slo, shi), for the column with FP32
+// affine parts (u0, v0, w0) and z-coefficients (uz, vz, wz).
+__device__ __forceinline__ BandCol band_interval(float u0, float v0, float w0, float uz, float vz, float wz,
+                                                 float zlo, float zhi, float tlo, float thi, float slo,
+                                                 float shi)
+{
+    BandCol r;
+    const float ya = fmaf(zlo, vz, v0) * __builtin_amdgcn_rcpf(fmaf(zlo, wz, w0));
+    const float yb = fmaf(zhi, vz, v0) * __builtin_amdgcn_rcpf(fmaf(zhi, wz, w0));
+    const float lo = tlo - 1.0f - kBandMargin, hi = thi + kBandMargin;   // v/w in [lo, hi]
+    r.za = zlo;
+    r.zb = zhi;
+    if (fmaxf(ya, yb) < lo || fminf(ya, yb) > hi) {
+        r.za = 1.0f;
+        r.zb = 0.0f;
+        return r;
+    }
+    const bool inc = yb >= ya;
+    const float sd = fabsf(vz) + fmaxf(fabsf(lo), fabsf(hi)) * fabsf(wz);
+    // entry crossing (v/w = lo when increasing, hi when decreasing) inside the slab
+    const float t_in = inc ? lo : hi, t_out = inc ? hi : lo;
+    if (inc ? ya < lo : ya > hi) {
+        const float d = fmaf(-t_in, wz, vz);
+        if (fabsf(d) > 1e-4f * sd) r.za = fmaxf(zlo, ceilf(fmaf(t_in, w0, -v0) / d - 1e-3f));
+    }
+    if (inc ? yb > hi : yb < lo) {
+        const float d = fmaf(-t_out, wz, vz);
+        if (fabsf(d) > 1e-4f * sd) r.zb = fminf(zhi, floorf(fmaf(t_out, w0, -v0) / d + 1e-3f));
+    }
+    if (r.za <= r.zb) {
+        const float xa = fmaf(r.za, uz, u0) * __builtin_amdgcn_rcpf(fmaf(r.za, wz, w0));
+        const float xb = fmaf(r.zb, uz, u0) * __builtin_amdgcn_rcpf(fmaf(r.zb, wz, w0));
+        if (fmaxf(xa, xb) < slo - 1.0f - kBandMargin || fminf(xa, xb) > shi + kBandMargin) {
+            r.za = 1.0f;
+            r.zb = 0.0f;
+        }
+    }
+    return r;
+}
+
+template <int P>
+__global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
+{
+    extern __shared__ double lds[];   // P tiles of tw x th, FP64 accumulators
+    const int groups = (b.n_proj + P - 1) / P;
+    // group-minor order: concurrently resident workgroups share the planes of
+    // one band of detector rows
+    const int tile = (int)(blockIdx.x / groups), g = (int)(blockIdx.x - tile * groups);
+    const int k0 = g * P, np = min(P, b.n_proj - k0);
+    const int tu = tile % b.tiles_u, tv = tile / b.tiles_u;
+    const int i0 = tu * b.tw, i1 = min(i0 + b.tw, b.W);
+    const int j0 = tv * b.th, j1 = min(j0 + b.th, b.H);
+    const int tw = i1 - i0, th = j1 - j0, tpx = tw * th;
+    for (int e = threadIdx.x; e < P * tpx; e += kBandThreads) lds[e] = 0.0;
+    __syncthreads();
+    const double* coef = b.coef + 16 * k0;
+    // the tile in centred detector coordinates
+    const float slo = (float)(i0 - b.cu), shi = (float)(i1 - b.cu);
+    const float tlo = (float)(j0 - b.cv), thi = (float)(j1 - b.cv);
+    const int64_t plane = (int64_t)b.L * b.L;
+    const float zlo = (float)(b.z_begin - b.ctr), zhi = (float)(b.z_begin + b.z_count - 1 - b.ctr);
+    // the workgroup walks 32 x 32 blocks of columns, each wavefront an 8 x 8
+    // patch of them: its samples then spread over >= 21 pixels whatever the
+    // angle, which keeps LDS address conflicts low
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int px = (wave & 3) * 8 + (lane & 7), py = (wave >> 2) * 8 + (lane >> 3);
+    const int nbx = (b.L + 31) >> 5, nblk = nbx * nbx;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int by = blk / nbx;
+        const int x = (blk - by * nbx) * 32 + px, y = by * 32 + py;
+        if (x >= b.L || y >= b.L) continue;
+        const float xf = (float)(x - b.ctr), yf = (float)(y - b.ctr);
+        BandCol iv[P];
+        float za = zhi + 1.0f, zb = zlo - 1.0f;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            iv[p].za = 1.0f;
+            iv[p].zb = 0.0f;
+            if (p < np) {
+                const double* c = coef + 16 * p;
+                const float u0 = fmaf(xf, (float)c[0], fmaf(yf, (float)c[1], (float)c[3]));
+                const float v0 = fmaf(xf, (float)c[4], fmaf(yf, (float)c[5], (float)c[7]));
+                const float w0 = fmaf(xf, (float)c[8], fmaf(yf, (float)c[9], (float)c[11]));
+                iv[p] = band_interval(u0, v0, w0, (float)c[2], (float)c[6], (float)c[10], zlo, zhi, tlo, thi, slo,
+                                      shi);
+                if (iv[p].za <= iv[p].zb) {
+                    za = fminf(za, iv[p].za);
+                    zb = fmaxf(zb, iv[p].zb);
+                }
+            }
+        }
+        if (za > zb) continue;
+        const int zl_a = (int)za + b.ctr - b.z_begin, zl_b = (int)zb + b.ctr - b.z_begin;
+        const int zmid = (zl_a + zl_b) >> 1;
+        const double xd = (double)(x - b.ctr), yd = (double)(y - b.ctr);
+        const double zd = (double)(b.z_begin + zmid - b.ctr);
+        // per projection: FP64 anchor at the middle plane, FP32 remainders
+        float sub[P], svb[P], swb[P], sdu[P], sdv[P];
+        int oi[P], oj[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double* c = coef + 16 * p;
+            const bool on = p < np && iv[p].za <= iv[p].zb;
+            const double ub = fma(xd, c[0], fma(yd, c[1], fma(zd, c[2], c[3])));
+            const double vb = fma(xd, c[4], fma(yd, c[5], fma(zd, c[6], c[7])));
+            const double wb = fma(xd, c[8], fma(yd, c[9], fma(zd, c[10], c[11])));
+            const float wf = (float)wb;
+            const float rf = __builtin_amdgcn_rcpf(wf);
+            const float fau = fminf(fmaxf(rintf((float)ub * rf), -1.0e6f), 1.0e6f);
+            const float fav = fminf(fmaxf(rintf((float)vb * rf), -1.0e6f), 1.0e6f);
+            sub[p] = (float)fma(-(double)fau, wb, ub);
+            svb[p] = (float)fma(-(double)fav, wb, vb);
+            swb[p] = wf;
+            sdu[p] = (float)fma(-(double)fau, c[10], c[2]);
+            sdv[p] = (float)fma(-(double)fav, c[10], c[6]);
+            // tap (i, j) relative to the tile; an inactive projection gets a
+            // row offset that keeps every tap outside
+            oi[p] = (int)fau + b.cu - i0;
+            oj[p] = on ? (int)fav + b.cv - j0 : -(1 << 28);
+        }
+        const float* in = b.vol + (int64_t)y * b.L + x;
+        for (int zl = zl_a; zl <= zl_b; ++zl) {
+            const float val0 = in[(int64_t)zl * plane];
+            if (val0 == 0.0f) continue;
+            const float t = (float)(zl - zmid);
+            const float vs = val0 * b.out_scale;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const double* c = coef + 16 * p;
+                const float u = fmaf(t, sdu[p], sub[p]), v = fmaf(t, sdv[p], svb[p]);
+                const float w = fmaf(t, (float)c[10], swb[p]);
+                const float r = __builtin_amdgcn_rcpf(w);
+                const float dx = __builtin_amdgcn_fmed3f(u * r, -2.0e6f, 2.0e6f);
+                const float dy = __builtin_amdgcn_fmed3f(v * r, -2.0e6f, 2.0e6f);
+                const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
+                const int ti = oi[p] + cvt_floor(dx), tj = oj[p] + cvt_floor(dy);
+                const float val = vs * (r * r);
+                const float bw = val * sy, tp = val - bw;
+                const bool c0 = (unsigned)ti < (unsigned)tw, c1 = (unsigned)(ti + 1) < (unsigned)tw;
+                const bool r0 = (unsigned)tj < (unsigned)th, r1 = (unsigned)(tj + 1) < (unsigned)th;
+                double* tl = lds + p * tpx + tj * tw + ti;
+                if (r0 && c0) __hip_atomic_fetch_add(tl, (double)(tp - tp * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (r0 && c1) __hip_atomic_fetch_add(tl + 1, (double)(tp * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (r1 && c0) __hip_atomic_fetch_add(tl + tw, (double)(bw - bw * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (r1 && c1) __hip_atomic_fetch_add(tl + tw + 1, (double)(bw * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < np; ++p) {
+        float* out = b.out + ((int64_t)(k0 + p) * b.H + j0) * b.W + i0;
+        const double* src = lds + p * tpx;
+        for (int e = threadIdx.x; e < tpx; e += kBandThreads) {
+            const int r = e / tw, cl = e - r * tw;
+            float* d = out + (int64_t)r * b.W + cl;
+            *d = b.accumulate ? (float)(src[e] + (double)*d) : (float)src[e];
+        }
+    }
+}
+
 // ----------------------------------------------------------------- staging
 // One padded row of the staged layout.  Pixel (ip, jp) of the padded image
 // is the detector pixel (ip - 2, jp - 2), zero outside the detector; the quad
@@ -979,12 +1164,44 @@ int batched_blocks_per_cu(int strip, int waves)
 
 hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, hipStream_t s)
 {
-    const int bx = waves >= 2 ? 2 : 1, by = waves / bx;
+    const int bx = waves >= 16 ? 4 : waves >= 2 ? 2 : 1, by = waves / bx;   // as Patch<NW>
     const int64_t n = (int64_t)a.tiles_x * a.tiles_y * a.tiles_z * a.n_proj;
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(window_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, strip, bx, by, out);
     return hipGetLastError();
+}
+
+int supported_band_group(int p) { return p == 1 || p == 2 || p == 4 || p == 8; }
+
+template <int P>
+static hipError_t launch_band(const BandArgs& b, hipStream_t s)
+{
+    const int groups = (b.n_proj + P - 1) / P;
+    const int64_t blocks = (int64_t)b.tiles_u * b.tiles_v * groups;
+    const size_t lds = (size_t)P * b.tw * b.th * sizeof(double);
+    if (blocks > 0x7fffffffLL || lds > (size_t)kBandCap * sizeof(double)) return hipErrorInvalidValue;
+    static bool attr_set = false;
+    if (!attr_set) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fp_band_kernel<P>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 kBandCap * (int)sizeof(double));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(fp_band_kernel<P>, dim3((unsigned)blocks), dim3(kBandThreads), lds, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fp_band(const BandArgs& b, int group, hipStream_t s)
+{
+    switch (group) {
+    case 1: return launch_band<1>(b, s);
+    case 2: return launch_band<2>(b, s);
+    case 4: return launch_band<4>(b, s);
+    case 8: return launch_band<8>(b, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_stage(const StageArgs& a, hipStream_t s)

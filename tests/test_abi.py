@@ -174,6 +174,19 @@ def test_tiles_and_tuning_file(fdk, tmp_path):
     assert fdk.get_tile(vol, fdk.F32) == fdk.get_tile(vol, fdk.F32)
 
 
+def test_adjoint_tiles(fdk):
+    vol = fdk.Volume(256, 1.0)
+    assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == (16, 1, 4)
+    for bad in [(16, 3, 4), (4096, 8, 4), (0, 1, 4), (16, 4, 3), (16, 4, 1), (5, 1, 0)]:
+        with pytest.raises(fdk.FdkError):
+            fdk.set_tile(fdk.TUNE_ADJOINT, *bad)
+    for good in [(1, 1, 4), (2560, 8, 4), (8, 2, 0)]:
+        fdk.set_tile(fdk.TUNE_ADJOINT, *good)
+        assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == good
+    fdk.set_tile(fdk.TUNE_ADJOINT, 0, 0)
+    assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == (16, 1, 4)
+
+
 def test_header_struct_layout(fdk):
     """The ctypes mirror has the sizes the C structs have."""
     assert ctypes.sizeof(fdk._Volume) == 48

@@ -37,6 +37,46 @@ def test_forwardproject_matches_oracle(fdk):
     assert_parity(out.cpu().numpy(), ref, what="forward projection")
 
 
+@pytest.mark.parametrize("strip,waves,layout", [(2, 1, 0), (8, 2, 0), (16, 4, 0), (32, 4, 0),
+                                                (1, 1, 4), (5, 2, 4), (13, 4, 4), (16, 1, 4), (77, 8, 4)])
+def test_forwardproject_every_shape(fdk, strip, waves, layout):
+    """Ragged grid (L = 37): direct global scatter for several strip shapes
+    and detector tiles of 1 to 77 rows for 1 to 8 projections per
+    workgroup."""
+    carm = small_carm(9, 101, 77)
+    mats = S.carm_matrices(carm)
+    L, voxel = 37, 4.0
+    x = torch.randn(L, L, L, generator=torch.Generator().manual_seed(5))
+    fdk.set_tile(fdk.TUNE_ADJOINT, strip, waves, layout)
+    try:
+        out = fdk.forwardproject(x.to(DEV), fdk.Geometry(mats, carm.width, carm.height), fdk.Volume(L, voxel))
+        torch.cuda.synchronize()
+    finally:
+        fdk.set_tile(fdk.TUNE_ADJOINT, 0, 0)
+    ref = oracle.forwardproject(L, voxel, mats, x.numpy(), carm.width, carm.height)
+    assert_parity(out.cpu().numpy(), ref, what=f"adjoint {strip}x{waves} layout {layout}")
+
+
+@pytest.mark.parametrize("rows,group", [(8, 2), (16, 4), (64, 1), (32, 8)])
+def test_forwardproject_detector_tiles_wide(fdk, rows, group):
+    """Detector tiles of the 1248 x 960 detector, rows x min(1248, 20480 /
+    (rows group)) pixels, so all but the first split the columns between
+    tiles; group projections share a workgroup; the volume is larger than the
+    field of view."""
+    carm = S.CArm(5)
+    mats = S.carm_matrices(carm)
+    L, voxel = 56, 4.5
+    x = torch.randn(L, L, L, generator=torch.Generator().manual_seed(8))
+    fdk.set_tile(fdk.TUNE_ADJOINT, rows, group, 4)
+    try:
+        out = fdk.forwardproject(x.to(DEV), fdk.Geometry(mats, carm.width, carm.height), fdk.Volume(L, voxel))
+        torch.cuda.synchronize()
+    finally:
+        fdk.set_tile(fdk.TUNE_ADJOINT, 0, 0)
+    ref = oracle.forwardproject(L, voxel, mats, x.numpy(), carm.width, carm.height)
+    assert_parity(out.cpu().numpy(), ref, what=f"detector tiles {rows} rows x {group}")
+
+
 def test_forwardproject_edges_and_accumulate(fdk):
     L, W, H, N, voxel = 19, 13, 9, 4, 1.0
     mats = S.tiny_cone_matrices(N, W, H, L, voxel, 5)
