@@ -33,10 +33,19 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_FP32_NONPACKED = 78.6    # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, without packed FP32
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "bp_f32_512x496_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1401_3615_amd", "csrc", "fdk_kernels.hip")
+COPY_BYTES = 1 << 30          # calibration kernel traffic each way (profile runs only)
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bp_kernel_name(fdk, vol) -> str:
+    """Name of the FP32 backprojection kernel the library launches for `vol`."""
+    strip, waves, layout = fdk.get_tile(vol, fdk.F32)
+    if layout == 3:
+        return f"bp_lds_kernel<float, {strip}, {waves}>"
+    return f"bp_kernel<float, {layout}, {strip}, {waves}>"
 
 
 def kernel_hash() -> str:
@@ -121,7 +130,15 @@ def main() -> int:
     value = updates / (ms * 1e-3) / 1e9
     log(f"fp32: {ms:.2f} ms/step, {value:.1f} GUp/s (bp kernel {bp_kernel_ms:.2f} ms, staging {stage_ms:.2f} ms)")
     if args.profile_only:
-        print(json.dumps({"metric": "fp32_gups", "value": value, "ms_per_step": ms}), flush=True)
+        # calibration for HBM counters: an elementwise kernel that reads and
+        # writes COPY_BYTES each
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"metric": "fp32_gups", "value": value, "ms_per_step": ms,
+                          "kernel": bp_kernel_name(fdk, vol), "copy_bytes_each_way": COPY_BYTES}), flush=True)
         return 0
     vol32 = out.clone()
 
@@ -204,7 +221,7 @@ def main() -> int:
             traffic = cnt["hbm_bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "kernel": "bp_kernel<float>", "kernel_ms": round(bp_kernel_ms, 3),
+                "kernel": bp_kernel_name(fdk, vol), "kernel_ms": round(bp_kernel_ms, 3),
                 "flop_per_update": FLOP_PER_UPDATE,
                 "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED, 4)}
 

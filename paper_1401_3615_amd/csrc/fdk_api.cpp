@@ -490,6 +490,7 @@ TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, Til
     a.cu = cu;
     a.cv = cv;
     a.win = nullptr;
+    a.rot_div = 0;
     return a;
 }
 

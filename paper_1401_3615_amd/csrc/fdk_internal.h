@@ -48,6 +48,7 @@ struct TileArgs {
     int32_t layout;              // 0 plain, 1 quad, 2 pair (global gathers), 3 LDS tiles
     const Win* win;              // layout 3: n_tiles x n_proj windows
     int32_t cu, cv;              // integer detector centre (W/2, H/2)
+    int32_t rot_div;             // projection-order rotation divisor (0: every tile starts at k = 0)
 };
 
 // Forward projection by detector-tile ownership: one workgroup per

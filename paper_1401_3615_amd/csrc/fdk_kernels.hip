@@ -25,6 +25,9 @@
 
 #include "fdk_internal.h"
 
+#include <algorithm>
+#include <map>
+
 namespace fdk {
 namespace {
 
@@ -304,24 +307,53 @@ __device__ __forceinline__ Coef load_coef(const double* tab, int k)
     return r;
 }
 
+// Projection order of a tile.  Workgroups start one after another as slots
+// free up, so with every tile starting at k = 0 the resident workgroups would
+// be spread over all projections and share nothing in L2.  Tile t instead
+// starts at k0 = t N / D (mod N), D = the number of workgroups resident at once
+// on one XCD (or on the device, for the persistent kernel): a workgroup that
+// starts later starts further on, and all resident workgroups then work on
+// about the same projection, whose footprint they share in L2.  The sum over k
+// is the same; only its FP32 rounding order depends on the tile.
+struct ProjOrder {
+    int k;                      // current projection
+    const unsigned char* img;   // its staged image
+    __device__ __forceinline__ ProjOrder(const TileArgs& a, int tile, int rot_div)
+    {
+        k = rot_div > 0 ? (int)(((int64_t)tile * a.n_proj / rot_div) % a.n_proj) : 0;
+        img = a.proj + (uint64_t)k * a.proj_stride;
+    }
+    __device__ __forceinline__ void advance(const TileArgs& a)
+    {
+        ++k;
+        img += a.proj_stride;
+        if (k == a.n_proj) {
+            k = 0;
+            img = a.proj;
+        }
+    }
+};
+
 // Backprojection of all projections into one tile: NW patches of 8 x 8
 // columns, S planes deep.
 template <typename T, int LAY, int S, int NW>
-__device__ __forceinline__ void bp_tile(const TileArgs& a, int tile)
+__device__ __forceinline__ void bp_tile(const TileArgs& a, int tile, int rot_div)
 {
     using Smp = Sampler<T, LAY>;
     const TilePos p = tile_pos<S, NW>(a, tile);
     float acc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = 0.0f;
-    const unsigned char* img = a.proj;
     const uint32_t row = a.row_bytes;
     const int wp = (int)(a.row_bytes >> Smp::kShift);
-    // coefficients of projection k+1 are fetched while projection k is processed
-    Coef next = load_coef(a.coef, 0);
-    for (int k = 0; k < a.n_proj; ++k, img += a.proj_stride) {
+    ProjOrder po(a, tile, rot_div);
+    // coefficients of the next projection are fetched while this one is processed
+    Coef next = load_coef(a.coef, po.k);
+    for (int n = 0; n < a.n_proj; ++n) {
         const Coef cur = next;
-        if (k + 1 < a.n_proj) next = load_coef(a.coef, k + 1);
+        const unsigned char* img = po.img;
+        po.advance(a);
+        if (n + 1 < a.n_proj) next = load_coef(a.coef, po.k);
         const Strip st = strip_setup<Smp::kShift>(cur.c, p, a, wp);
         if (__builtin_amdgcn_ballot_w64(strip_touches<S>(st)) == 0) continue;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
@@ -356,19 +388,19 @@ __device__ __forceinline__ void bp_tile(const TileArgs& a, int tile)
 }
 
 template <int LAY, int S, int NW>
-__device__ __forceinline__ void bp_tile_lay(const TileArgs& a, int tile)
+__device__ __forceinline__ void bp_tile_lay(const TileArgs& a, int tile, int rot_div)
 {
-    if (a.dtype == 1) bp_tile<__half, LAY, S, NW>(a, tile);
-    else if (a.dtype == 2) bp_tile<bf16_t, LAY, S, NW>(a, tile);
-    else bp_tile<float, LAY, S, NW>(a, tile);
+    if (a.dtype == 1) bp_tile<__half, LAY, S, NW>(a, tile, rot_div);
+    else if (a.dtype == 2) bp_tile<bf16_t, LAY, S, NW>(a, tile, rot_div);
+    else bp_tile<float, LAY, S, NW>(a, tile, rot_div);
 }
 
 template <int S, int NW>
-__device__ __forceinline__ void bp_tile_any(const TileArgs& a, int tile)
+__device__ __forceinline__ void bp_tile_any(const TileArgs& a, int tile, int rot_div)
 {
-    if (a.layout == 1) bp_tile_lay<1, S, NW>(a, tile);
-    else if (a.layout == 2) bp_tile_lay<2, S, NW>(a, tile);
-    else bp_tile_lay<0, S, NW>(a, tile);
+    if (a.layout == 1) bp_tile_lay<1, S, NW>(a, tile, rot_div);
+    else if (a.layout == 2) bp_tile_lay<2, S, NW>(a, tile, rot_div);
+    else bp_tile_lay<0, S, NW>(a, tile, rot_div);
 }
 
 // Register budget: longer strips keep more taps in flight, so they are allowed
@@ -381,7 +413,7 @@ __global__ __launch_bounds__(kWave * NW)
     __attribute__((amdgpu_waves_per_eu(waves_per_eu<S>(), waves_per_eu<S>()))) void bp_kernel(TileArgs a)
 {
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    bp_tile<T, LAY, S, NW>(a, tile);
+    bp_tile<T, LAY, S, NW>(a, tile, a.rot_div);
 }
 
 // ----------------------------------------------------------------- LDS tiles
@@ -484,6 +516,69 @@ constexpr int lds_waves_per_eu()
     return (5 * NW / 4) < 1 ? 1 : ((5 * NW / 4) < waves_per_eu<S>() ? (5 * NW / 4) : waves_per_eu<S>());
 }
 
+// The window of one projection as the LDS tile holds it: 4-pixel chunks
+// [c_lo, c_hi] x [j0, j1] of the staged image, row pitch tw pixels.
+struct LdsWin {
+    int c_lo, c_hi, j0, j1, tw, th, nc, total;   // total = chunks = nc * th
+    bool empty, fits;
+    __device__ __forceinline__ explicit LdsWin(Win w)
+    {
+        empty = w.i0 > w.i1;
+        c_lo = w.i0 & ~3;
+        c_hi = w.i1 | 3;
+        j0 = w.j0;
+        j1 = w.j1;
+        tw = c_hi - c_lo + 1;
+        th = j1 - j0 + 1;
+        nc = tw >> 2;
+        total = empty ? 0 : nc * th;
+        fits = !empty && tw * th <= kLdsCap;
+    }
+};
+
+// Chunks of a window prefetched into registers per thread while the previous
+// projection is sampled (kPre x 256 threads x 4 pixels = 4096 pixels for a
+// 4-wave workgroup); larger windows load their remainder after the barrier.
+constexpr int kPre = 4;
+
+template <typename T, int NW>
+__device__ __forceinline__ void window_prefetch(float4 (&pre)[kPre], const LdsWin& w, __amdgpu_buffer_rsrc_t rs,
+                                                int wp)
+{
+    const float inv_nc = 1.0f / (float)w.nc;
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) {
+        const int e = (int)threadIdx.x + i * kWave * NW;
+        if (e < w.total) {
+            const int r = (int)(((float)e + 0.5f) * inv_nc);
+            const int cc = e - r * w.nc;
+            pre[i] = Chunk<T>::load(rs, (uint32_t)((w.j0 + r) * wp + w.c_lo + 4 * cc));
+        }
+    }
+}
+
+template <typename T, int NW>
+__device__ __forceinline__ void window_store(float* lds, const float4 (&pre)[kPre], const LdsWin& w,
+                                             __amdgpu_buffer_rsrc_t rs, int wp)
+{
+    const float inv_nc = 1.0f / (float)w.nc;
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) {
+        const int e = (int)threadIdx.x + i * kWave * NW;
+        if (e < w.total) {
+            const int r = (int)(((float)e + 0.5f) * inv_nc);
+            const int cc = e - r * w.nc;
+            *reinterpret_cast<float4*>(&lds[r * w.tw + 4 * cc]) = pre[i];
+        }
+    }
+    for (int e = (int)threadIdx.x + kPre * kWave * NW; e < w.total; e += kWave * NW) {
+        const int r = (int)(((float)e + 0.5f) * inv_nc);
+        const int cc = e - r * w.nc;
+        *reinterpret_cast<float4*>(&lds[r * w.tw + 4 * cc]) =
+            Chunk<T>::load(rs, (uint32_t)((w.j0 + r) * wp + w.c_lo + 4 * cc));
+    }
+}
+
 template <typename T, int S, int NW>
 __global__ __launch_bounds__(kWave * NW)
     __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<S, NW>(), lds_waves_per_eu<S, NW>()))) void bp_lds_kernel(TileArgs a)
@@ -494,38 +589,38 @@ __global__ __launch_bounds__(kWave * NW)
     float acc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = 0.0f;
-    const unsigned char* img = a.proj;
     const uint32_t row = a.row_bytes;
     const int wp = (int)(a.row_bytes / sizeof(T));
     const Win* wins = a.win + (int64_t)tile * a.n_proj;
-    Coef next = load_coef(a.coef, 0);
-    for (int k = 0; k < a.n_proj; ++k, img += a.proj_stride) {
+    ProjOrder po(a, tile, a.rot_div);
+    Coef next = load_coef(a.coef, po.k);
+    // software pipeline: the window of the projection after this one is
+    // loaded into registers while this one is sampled from LDS
+    float4 pre[kPre];
+    LdsWin wv(wins[po.k]);
+    if (wv.fits) window_prefetch<T, NW>(pre, wv, make_rsrc(po.img, a.proj_bytes), wp);
+    for (int n = 0; n < a.n_proj; ++n) {
         const Coef cur = next;
-        if (k + 1 < a.n_proj) next = load_coef(a.coef, k + 1);
-        const Win wv = wins[k];
-        if (wv.i0 > wv.i1) continue;                        // tile clipped for this projection
-        const int c_lo = wv.i0 & ~3, c_hi = wv.i1 | 3;
-        const int tw = c_hi - c_lo + 1, th = wv.j1 - wv.j0 + 1;
+        const unsigned char* img = po.img;
+        po.advance(a);
+        const bool more = n + 1 < a.n_proj;
+        if (more) next = load_coef(a.coef, po.k);
+        const LdsWin wn(more ? wins[po.k] : Win{1, 0, 1, 0});
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
-        if (tw * th <= kLdsCap) {
+        const __amdgpu_buffer_rsrc_t rs_next = make_rsrc(po.img, a.proj_bytes);
+        if (wv.fits) {
             __syncthreads();                                // previous projection's reads are done
-            const int nc = tw >> 2, total = nc * th;
-            const float inv_nc = 1.0f / (float)nc;
-            for (int e = threadIdx.x; e < total; e += kWave * NW) {
-                const int r = (int)(((float)e + 0.5f) * inv_nc);
-                const int cc = e - r * nc;
-                const float4 v = Chunk<T>::load(rs, (uint32_t)((wv.j0 + r) * wp + c_lo + 4 * cc));
-                *reinterpret_cast<float4*>(&lds[r * tw + 4 * cc]) = v;
-            }
+            window_store<T, NW>(lds, pre, wv, rs, wp);
             __syncthreads();
+            if (wn.fits) window_prefetch<T, NW>(pre, wn, rs_next, wp);
             const Strip st = strip_setup<2>(cur.c, p, a, wp);
             // anchor in staged-pixel coordinates; clamp so both tap columns
             // and rows stay inside the window held in LDS
             const float ax = st.fau + (float)(a.cu + kPadLo), ay = st.fav + (float)(a.cv + kPadLo);
-            const float lox = (float)c_lo - ax, hix = (float)(c_hi - 1) - ax;
+            const float lox = (float)wv.c_lo - ax, hix = (float)(wv.c_hi - 1) - ax;
             const float loy = (float)wv.j0 - ay, hiy = (float)(wv.j1 - 1) - ay;
-            const int base = (((int)ay - wv.j0) * tw + ((int)ax - c_lo)) * 4;
-            const uint32_t row_l = (uint32_t)tw * 4;
+            const int base = (((int)ay - wv.j0) * wv.tw + ((int)ax - wv.c_lo)) * 4;
+            const uint32_t row_l = (uint32_t)wv.tw * 4;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 constexpr int kMid = S / 2;
@@ -537,7 +632,7 @@ __global__ __launch_bounds__(kWave * NW)
                 const float dx = __builtin_amdgcn_fmed3f(u * r, lox, hix);
                 const float dy = __builtin_amdgcn_fmed3f(v * r, loy, hiy);
                 const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
-                const uint32_t off = tap_offset<2>(cvt_floor(dx), cvt_floor(dy), tw, base);
+                const uint32_t off = tap_offset<2>(cvt_floor(dx), cvt_floor(dy), wv.tw, base);
                 const float* q0 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off);
                 const float* q1 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off + row_l);
                 const float top = fmaf(sx, q0[1] - q0[0], q0[0]);
@@ -546,24 +641,29 @@ __global__ __launch_bounds__(kWave * NW)
                 acc[s] = fmaf(val, r * r, acc[s]);
             }
         } else {
-            // window larger than the LDS tile: gather from the staged image
-            const Strip st = strip_setup<Sampler<T, 0>::kShift>(cur.c, p, a, wp);
+            if (wn.fits) window_prefetch<T, NW>(pre, wn, rs_next, wp);
+            if (!wv.empty) {
+                // window larger than the LDS tile: gather from the staged image
+                const Strip st = strip_setup<Sampler<T, 0>::kShift>(cur.c, p, a, wp);
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                constexpr int kMid = S / 2;
-                const float t = (float)(s - kMid);
-                const float u = fmaf(t, st.du, st.ub);
-                const float v = fmaf(t, st.dv, st.vb);
-                const float w = fmaf(t, st.dw, st.wb);
-                const float r = __builtin_amdgcn_rcpf(w);
-                const float dx = __builtin_amdgcn_fmed3f(u * r, st.lox, st.hix);
-                const float dy = __builtin_amdgcn_fmed3f(v * r, st.loy, st.hiy);
-                const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
-                const uint32_t off = tap_offset<Sampler<T, 0>::kShift>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
-                const float val = Sampler<T, 0>::sample(rs, off, row, sx, sy);
-                acc[s] = fmaf(val, r * r, acc[s]);
+                for (int s = 0; s < S; ++s) {
+                    constexpr int kMid = S / 2;
+                    const float t = (float)(s - kMid);
+                    const float u = fmaf(t, st.du, st.ub);
+                    const float v = fmaf(t, st.dv, st.vb);
+                    const float w = fmaf(t, st.dw, st.wb);
+                    const float r = __builtin_amdgcn_rcpf(w);
+                    const float dx = __builtin_amdgcn_fmed3f(u * r, st.lox, st.hix);
+                    const float dy = __builtin_amdgcn_fmed3f(v * r, st.loy, st.hiy);
+                    const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
+                    const uint32_t off =
+                        tap_offset<Sampler<T, 0>::kShift>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
+                    const float val = Sampler<T, 0>::sample(rs, off, row, sx, sy);
+                    acc[s] = fmaf(val, r * r, acc[s]);
+                }
             }
         }
+        wv = wn;
     }
     if (p.x < a.L && p.y < a.L) {
         const int64_t plane = (int64_t)a.L * a.L;
@@ -604,7 +704,7 @@ __global__ __launch_bounds__(kWave * NW)
         }
         const TileArgs a = scans[lo];
         const int tile = item - item_begin[lo];
-        bp_tile_any<S, NW>(a, tile);
+        bp_tile_any<S, NW>(a, tile, (int)gridDim.x);
     }
 }
 
@@ -1050,15 +1150,39 @@ __global__ void zero_u32_kernel(unsigned* p, int n)
 }
 
 // ----------------------------------------------------------------- dispatch
+// Workgroups of `kernel` resident at once on one XCD (eight XCDs share the
+// device's CUs); cached per kernel.  Callers hold the library lock.
+int resident_per_xcd(const void* kernel, int threads)
+{
+    static std::map<const void*, int> cache;
+    auto it = cache.find(kernel);
+    if (it != cache.end()) return it->second;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+        return 0;   // no rotation
+    const int r = std::max(1, cus / 8) * std::max(1, per_cu);
+    cache[kernel] = r;
+    return r;
+}
+
+template <typename K>
+void launch_rotated(K kernel, TileArgs a, dim3 grid, dim3 block, hipStream_t st)
+{
+    a.rot_div = resident_per_xcd(reinterpret_cast<const void*>(kernel), (int)block.x);
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, a);
+}
+
 template <int LAY, int S, int NW>
 void bp_dispatch_q(const TileArgs& a, dim3 grid, dim3 block, hipStream_t st)
 {
     if (a.dtype == 1)
-        hipLaunchKernelGGL((bp_kernel<__half, LAY, S, NW>), grid, block, 0, st, a);
+        launch_rotated(bp_kernel<__half, LAY, S, NW>, a, grid, block, st);
     else if (a.dtype == 2)
-        hipLaunchKernelGGL((bp_kernel<bf16_t, LAY, S, NW>), grid, block, 0, st, a);
+        launch_rotated(bp_kernel<bf16_t, LAY, S, NW>, a, grid, block, st);
     else
-        hipLaunchKernelGGL((bp_kernel<float, LAY, S, NW>), grid, block, 0, st, a);
+        launch_rotated(bp_kernel<float, LAY, S, NW>, a, grid, block, st);
 }
 
 template <int S, int NW>
@@ -1067,11 +1191,11 @@ hipError_t bp_dispatch_t(const TileArgs& a, int nblocks, hipStream_t st)
     dim3 grid(nblocks), block(kWave * NW);
     if (a.layout == 3) {
         if (a.dtype == 1)
-            hipLaunchKernelGGL((bp_lds_kernel<__half, S, NW>), grid, block, 0, st, a);
+            launch_rotated(bp_lds_kernel<__half, S, NW>, a, grid, block, st);
         else if (a.dtype == 2)
-            hipLaunchKernelGGL((bp_lds_kernel<bf16_t, S, NW>), grid, block, 0, st, a);
+            launch_rotated(bp_lds_kernel<bf16_t, S, NW>, a, grid, block, st);
         else
-            hipLaunchKernelGGL((bp_lds_kernel<float, S, NW>), grid, block, 0, st, a);
+            launch_rotated(bp_lds_kernel<float, S, NW>, a, grid, block, st);
         return hipGetLastError();
     }
     if (a.layout == 1)

@@ -58,7 +58,11 @@ def test_batched_matches_single_and_oracle(fdk):
         for sc, (L, voxel, mats, q, qd, scale) in zip(scans, host):
             single = fdk.backproject(sc.proj, sc.geom, sc.vol, scale=sc.scale)
             torch.cuda.synchronize()
-            assert torch.equal(single, sc.out), "batched differs from one launch per scan"
+            # same samples and weights; the persistent kernel rotates each tile's
+            # projection order by the device-wide residency instead of the
+            # per-XCD one, so only the FP32 summation order differs
+            assert oracle.rel_l2(sc.out.cpu().numpy(), single.cpu().numpy()) < 1e-6, \
+                "batched differs from one launch per scan"
             if scale is None:
                 ref = oracle.backproject(L, voxel, mats, q.numpy())
             else:
