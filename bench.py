@@ -76,8 +76,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    ap.add_argument("--legs", default="fp16,bf16,adjoint,batched,slab1024",
-                    help="comma list of extra legs (fp16,bf16,adjoint,batched,slab1024) or 'none'")
+    ap.add_argument("--legs", default="fp16,bf16,tilted,adjoint,batched,slab1024",
+                    help="comma list of extra legs (fp16,bf16,tilted,adjoint,batched,slab1024) or 'none'")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only warm-up and timed FP32 steps (for profiler runs)")
     args = ap.parse_args()
@@ -158,6 +158,20 @@ def main() -> int:
         extra[f"{name}_pack_ms"] = pk_ms
         log(f"{name}: {m:.2f} ms/step, {extra[f'{name}_gups']:.1f} GUp/s (pack {pk_ms:.2f} ms, not in step)")
         del qp, sc
+
+    # ---------------------------------------------------------------- general path
+    if "tilted" in legs:
+        # the same workload on a C-arm tilted by 0.5 degree: w varies along z,
+        # so the kernel takes 1/w per voxel (as for calibrated real systems)
+        carm_t = S.CArm(N, tilt_deg=0.5)
+        mats_t, q_t = S.filtered_projections(carm_t, seed=0, device=dev)
+        q_t = q_t.contiguous()
+        geom_t = fdk.Geometry(mats_t, carm_t.width, carm_t.height)
+        m = time_steps(lambda: fdk.backproject(q_t, geom_t, vol, out=out), args.steps, args.warmup, stream)
+        extra["tilted_gups"] = updates / (m * 1e-3) / 1e9
+        extra["tilted_ms_per_step"] = m
+        log(f"fp32, C-arm tilted 0.5 deg (per-voxel 1/w): {m:.2f} ms/step, {extra['tilted_gups']:.1f} GUp/s")
+        del q_t
 
     # ---------------------------------------------------------------- adjoint
     if "adjoint" in legs:

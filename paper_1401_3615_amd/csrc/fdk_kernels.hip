@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <map>
+#include <type_traits>
 
 namespace fdk {
 namespace {
@@ -293,6 +294,60 @@ __device__ __forceinline__ bool strip_touches(const Strip& st)
            fmaxf(y0, y1) > st.loy + m && fminf(y0, y1) < st.hiy - m;
 }
 
+// Sample coordinates along a strip.  In general 1/w is taken per voxel.  When
+// w does not change along z (the projection's depth axis is perpendicular to
+// the z axis, dw = 0 exactly, as for a circular orbit about z), 1/w is one
+// reciprocal per strip and the remainders u/w, v/w step linearly: two FMAs per
+// voxel instead of a reciprocal and two multiplies.  The choice is uniform per
+// projection.
+template <bool CONSTW>
+struct Walk {
+    float ax, bx, ay, by, aw, bw, r2;
+    __device__ __forceinline__ explicit Walk(const Strip& st)
+    {
+        if (CONSTW) {
+            const float r = __builtin_amdgcn_rcpf(st.wb);
+            ax = st.ub * r;
+            bx = st.du * r;
+            ay = st.vb * r;
+            by = st.dv * r;
+            r2 = r * r;
+            aw = bw = 0.0f;
+        } else {
+            ax = st.ub;
+            bx = st.du;
+            ay = st.vb;
+            by = st.dv;
+            aw = st.wb;
+            bw = st.dw;
+            r2 = 0.0f;
+        }
+    }
+    // remainders (dx, dy) and weight 1/w^2 of the voxel at offset t from the anchor
+    __device__ __forceinline__ void at(float t, float& dx, float& dy, float& wgt) const
+    {
+        if (CONSTW) {
+            dx = fmaf(t, bx, ax);
+            dy = fmaf(t, by, ay);
+            wgt = r2;
+        } else {
+            const float r = __builtin_amdgcn_rcpf(fmaf(t, bw, aw));
+            dx = fmaf(t, bx, ax) * r;
+            dy = fmaf(t, by, ay) * r;
+            wgt = r * r;
+        }
+    }
+};
+
+// Runs body(std::true_type) when projection c has w constant along z, else
+// body(std::false_type).
+template <typename F>
+__device__ __forceinline__ void with_walk(const double* c, F&& body)
+{
+    if (c[10] == 0.0) body(std::true_type{});
+    else body(std::false_type{});
+}
+
 // The 12 FP64 coefficients of projection k (16 are stored per projection).
 struct Coef {
     double c[12];
@@ -357,21 +412,21 @@ __device__ __forceinline__ void bp_tile(const TileArgs& a, int tile, int rot_div
         const Strip st = strip_setup<Smp::kShift>(cur.c, p, a, wp);
         if (__builtin_amdgcn_ballot_w64(strip_touches<S>(st)) == 0) continue;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
+        with_walk(cur.c, [&](auto cw) {
+            const Walk<decltype(cw)::value> wk(st);
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            constexpr int kMid = S / 2;
-            const float t = (float)(s - kMid);
-            const float u = fmaf(t, st.du, st.ub);
-            const float v = fmaf(t, st.dv, st.vb);
-            const float w = fmaf(t, st.dw, st.wb);
-            const float r = __builtin_amdgcn_rcpf(w);
-            const float dx = __builtin_amdgcn_fmed3f(u * r, st.lox, st.hix);
-            const float dy = __builtin_amdgcn_fmed3f(v * r, st.loy, st.hiy);
-            const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
-            const uint32_t off = tap_offset<Smp::kShift>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
-            const float val = Smp::sample(rs, off, row, sx, sy);
-            acc[s] = fmaf(val, r * r, acc[s]);
-        }
+            for (int s = 0; s < S; ++s) {
+                constexpr int kMid = S / 2;
+                float ux, uy, wgt;
+                wk.at((float)(s - kMid), ux, uy, wgt);
+                const float dx = __builtin_amdgcn_fmed3f(ux, st.lox, st.hix);
+                const float dy = __builtin_amdgcn_fmed3f(uy, st.loy, st.hiy);
+                const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
+                const uint32_t off = tap_offset<Smp::kShift>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
+                const float val = Smp::sample(rs, off, row, sx, sy);
+                acc[s] = fmaf(val, wgt, acc[s]);
+            }
+        });
     }
     if (p.x < a.L && p.y < a.L) {
         const int64_t plane = (int64_t)a.L * a.L;
@@ -621,25 +676,26 @@ __global__ __launch_bounds__(kWave * NW)
             const float loy = (float)wv.j0 - ay, hiy = (float)(wv.j1 - 1) - ay;
             const int base = (((int)ay - wv.j0) * wv.tw + ((int)ax - wv.c_lo)) * 4;
             const uint32_t row_l = (uint32_t)wv.tw * 4;
+            with_walk(cur.c, [&](auto cw) {
+                const Walk<decltype(cw)::value> wk(st);
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                constexpr int kMid = S / 2;
-                const float t = (float)(s - kMid);
-                const float u = fmaf(t, st.du, st.ub);
-                const float v = fmaf(t, st.dv, st.vb);
-                const float w = fmaf(t, st.dw, st.wb);
-                const float r = __builtin_amdgcn_rcpf(w);
-                const float dx = __builtin_amdgcn_fmed3f(u * r, lox, hix);
-                const float dy = __builtin_amdgcn_fmed3f(v * r, loy, hiy);
-                const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
-                const uint32_t off = tap_offset<2>(cvt_floor(dx), cvt_floor(dy), wv.tw, base);
-                const float* q0 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off);
-                const float* q1 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off + row_l);
-                const float top = fmaf(sx, q0[1] - q0[0], q0[0]);
-                const float bot = fmaf(sx, q1[1] - q1[0], q1[0]);
-                const float val = fmaf(sy, bot - top, top);
-                acc[s] = fmaf(val, r * r, acc[s]);
-            }
+                for (int s = 0; s < S; ++s) {
+                    constexpr int kMid = S / 2;
+                    float ux, uy, wgt;
+                    wk.at((float)(s - kMid), ux, uy, wgt);
+                    const float dx = __builtin_amdgcn_fmed3f(ux, lox, hix);
+                    const float dy = __builtin_amdgcn_fmed3f(uy, loy, hiy);
+                    const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
+                    const uint32_t off = tap_offset<2>(cvt_floor(dx), cvt_floor(dy), wv.tw, base);
+                    const float* q0 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off);
+                    const float* q1 =
+                        reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off + row_l);
+                    const float top = fmaf(sx, q0[1] - q0[0], q0[0]);
+                    const float bot = fmaf(sx, q1[1] - q1[0], q1[0]);
+                    const float val = fmaf(sy, bot - top, top);
+                    acc[s] = fmaf(val, wgt, acc[s]);
+                }
+            });
         } else {
             if (wn.fits) window_prefetch<T, NW>(pre, wn, rs_next, wp);
             if (!wv.empty) {

@@ -46,6 +46,7 @@ class CArm:
     sdd: float = 1200.0     # source to detector
     pixel: float = 0.308    # detector pixel pitch
     arc_deg: float = 200.0  # short-scan arc
+    tilt_deg: float = 0.0   # camera frame tilted about its u axis (0: the orbit plane is the mid-plane)
 
     @property
     def focal_px(self) -> float:
@@ -67,8 +68,10 @@ def carm_matrices(carm: CArm) -> np.ndarray:
 
     Camera frame: x_cam = e_u (tangential, the direction the source moves),
     y_cam = (0, 0, -1) (detector rows run along -z), z_cam = e_d (from the
-    source towards the isocentre).  The third row of [R|t] has unit norm, so w
-    is the source-to-voxel depth along the central ray in mm.
+    source towards the isocentre); with tilt_deg the camera frame is turned
+    about x_cam, so the depth axis leaves the orbit plane (as in calibrated
+    real C-arms) and w depends on z.  The third row of [R|t] has unit norm, so
+    w is the source-to-voxel depth along the central ray in mm.
     """
     f = carm.focal_px
     cu, cv = carm.principal_point
@@ -78,6 +81,9 @@ def carm_matrices(carm: CArm) -> np.ndarray:
         c, s = math.cos(th), math.sin(th)
         src = carm.sid * np.array([c, s, 0.0])
         R = np.array([[-s, c, 0.0], [0.0, 0.0, -1.0], [-c, -s, 0.0]])
+        if carm.tilt_deg != 0.0:
+            ct, st = math.cos(math.radians(carm.tilt_deg)), math.sin(math.radians(carm.tilt_deg))
+            R = np.array([[1.0, 0.0, 0.0], [0.0, ct, -st], [0.0, st, ct]]) @ R
         t = -R @ src
         mats[k] = K @ np.concatenate([R, t[:, None]], axis=1)
     return mats

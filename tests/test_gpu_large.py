@@ -77,6 +77,19 @@ def test_512_fp32_full_planes(fdk, c1):
         assert err <= REL_L2_FP32
 
 
+def test_512_fp32_tilted_sampled(fdk):
+    """512^3 x 496 on a C-arm tilted by 0.5 degree (w varies along z: the
+    per-voxel reciprocal path) at sampled voxels."""
+    carm = S.CArm(496, tilt_deg=0.5)
+    mats, q = S.filtered_projections(carm, 0, device=DEV)
+    L, voxel = 512, 0.5
+    out = fdk.backproject(q.contiguous(), fdk.Geometry(mats, carm.width, carm.height), fdk.Volume(L, voxel))
+    torch.cuda.synchronize()
+    xyz = sample_voxels(L, 2000, 14)
+    ref = oracle.backproject_points(xyz, voxel, mats, q.cpu().numpy().astype(np.float64), L=L)
+    check_points(out, xyz, ref, "512^3 fp32 tilted C-arm")
+
+
 @pytest.mark.parametrize("dtype,total_bound", [(torch.float16, 1e-3), (torch.bfloat16, 1e-2)])
 def test_512_packed_sampled(fdk, c1, dtype, total_bound):
     """FP16/BF16 storage: the kernel error (against the oracle run on the
