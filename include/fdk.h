@@ -64,8 +64,11 @@ typedef enum fdk_dtype {
     FDK_BF16 = 2   /* bfloat16 */
 } fdk_dtype;
 
-/* Tuning slot of the forward projector (fdk_set_tile and the tuning table). */
+/* Tuning slots besides the three projection dtypes (fdk_set_tile and the
+ * tuning table): the forward projector, and the tile shape of the batched
+ * persistent launch. */
 #define FDK_TUNE_ADJOINT 3
+#define FDK_TUNE_BATCHED 4
 
 /* The volume grid (paper: edge L, voxel pitch MM, origin O).  The buffer
  * passed with it holds the planes [z_begin, z_begin + z_count), which lets a
@@ -176,7 +179,9 @@ fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width,
  * memory, aligned row loads); layout 3 copies each workgroup's projection
  * window into LDS and reads the taps there.  The `dtype` argument selects a
  * tuning slot: FDK_F32, FDK_F16, FDK_BF16 (backprojection by projection
- * dtype) or FDK_TUNE_ADJOINT (the forward projector).  For the forward
+ * dtype), FDK_TUNE_BATCHED (strip and waves of fdk_backproject_batched, and
+ * the layout of its FP32 scans; FP16/BF16 scans keep the layout of their own
+ * slot) or FDK_TUNE_ADJOINT (the forward projector).  For the forward
  * projector, layout 4 (the default) gives each workgroup a detector tile of
  * `strip` rows (1 <= strip, strip * waves <= 20480) by
  * min(width, 20480 / (strip * waves)) pixels in `waves` projections

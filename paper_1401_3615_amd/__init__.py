@@ -21,7 +21,7 @@ import torch  # loads the HIP runtime that libfdk.so binds to
 from . import _build
 
 __all__ = [
-    "FdkError", "Volume", "Geometry", "F32", "F16", "BF16", "TUNE_ADJOINT", "load", "backproject",
+    "FdkError", "Volume", "Geometry", "F32", "F16", "BF16", "TUNE_ADJOINT", "TUNE_BATCHED", "load", "backproject",
     "forwardproject", "backproject_batched", "pack_projections", "set_tile", "get_tile",
     "load_tuning", "set_tuning_entry", "validate", "release_workspace", "abi_version",
     "BackProject", "ForwardProject", "Scan", "profile_enable", "profile_read",
@@ -29,6 +29,7 @@ __all__ = [
 
 F32, F16, BF16 = 0, 1, 2
 TUNE_ADJOINT = 3   # tuning slot of the forward projector
+TUNE_BATCHED = 4   # tuning slot of the batched persistent launch
 _TORCH_DTYPE = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
 
 

@@ -218,11 +218,13 @@ struct TileShape { int strip, waves, layout; };
 
 // Tuning slots: FDK_F32, FDK_F16, FDK_BF16 for the backprojection, and one for
 // the adjoint (forward projection).
-constexpr int kAdjointSlot = 3;
+constexpr int kAdjointSlot = FDK_TUNE_ADJOINT;
+constexpr int kBatchedSlot = FDK_TUNE_BATCHED;
+constexpr int kSlots = 5;
 
 struct Tuning {
     std::map<std::pair<int, int>, TileShape> table;  // (dtype, size class) -> shape
-    TileShape forced[4] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // index 3: adjoint
+    TileShape forced[kSlots] = {};   // by slot: FP32, FP16, BF16, adjoint, batched
     bool env_loaded = false;
 };
 
@@ -297,8 +299,17 @@ struct CoefEntry {
 struct BatchEntry {
     std::string key;
     hipGraphExec_t exec = nullptr;
-    DevBuf tiles, item_begin, stage, scale_ptrs, coef64, coef_dev, counter;
+    DevBuf tiles, item_begin, stage, scale_ptrs, coef64, coef_dev, counter, windows;
 };
+
+void release_entry(BatchEntry& b)
+{
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    b.exec = nullptr;
+    for (DevBuf* x : {&b.tiles, &b.item_begin, &b.stage, &b.scale_ptrs, &b.coef64, &b.coef_dev, &b.counter,
+                      &b.windows})
+        release(*x);
+}
 
 struct DeviceState {
     bool init = false;
@@ -417,9 +428,6 @@ fdk_status coef_table(DeviceState& d, const fdk_volume* v, const fdk_projections
 int pixel_bytes(int esize, int layout) { return layout == 1 ? 4 * esize : layout == 2 ? 2 * esize : esize; }
 // Layout 3 (LDS tiles) reads the plain staged image.
 int staged_layout(int layout) { return layout == 3 ? 0 : layout; }
-// The persistent batched kernel gathers from staged images; layout 3 maps to
-// the plain gather there.
-int batched_layout(int layout) { return layout == 3 ? 0 : layout; }
 
 // The quad layout multiplies the staged image by four; images whose quad form
 // would not fit 31-bit offsets use the plain layout.
@@ -436,7 +444,8 @@ TileShape pick_tile(int L, int dtype)
     if (f.strip > 0) return f;
     auto it = g_tune.table.find({dtype, size_class(L)});
     if (it != g_tune.table.end()) return it->second;
-    return dtype == kAdjointSlot ? default_adjoint_tile(L) : default_tile(L, dtype);
+    if (dtype == kAdjointSlot) return default_adjoint_tile(L);
+    return default_tile(L, dtype == kBatchedSlot ? FDK_F32 : dtype);
 }
 
 bool valid_shape(int slot, TileShape t)
@@ -754,7 +763,14 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
     }
     std::lock_guard<std::mutex> lock(g_mu);
     load_env_tuning();
-    const TileShape t = pick_tile(maxL, FDK_F32);
+    // one tile shape (strip, waves) for the whole batch, from the batched slot;
+    // FP32 scans take its layout, FP16/BF16 scans the layout of their own slot
+    const TileShape t = pick_tile(maxL, kBatchedSlot);
+    auto scan_layout = [&](const fdk_projections* p) {
+        TileShape ts = t;
+        if (p->dtype != FDK_F32) ts.layout = pick_tile(maxL, p->dtype).layout;
+        return fit_layout(ts, p, esize_of(p->dtype)).layout;
+    };
     DeviceState* d = nullptr;
     fdk_status st = device_state(&d);
     if (st != FDK_OK) return st;
@@ -764,13 +780,11 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
     std::string key;
     auto put = [&key](const void* x, size_t n) { key.append(static_cast<const char*>(x), n); };
     put(&t, sizeof(t));
-    for (int dt = 0; dt < 3; ++dt) {
-        const int lay = batched_layout(pick_tile(maxL, dt).layout);
-        put(&lay, sizeof(int));
-    }
     put(&accumulate, sizeof(int));
     for (int i = 0; i < n_scans; ++i) {
         const fdk_scan& sc = scans[i];
+        const int lay = scan_layout(&sc.proj);
+        put(&lay, sizeof(int));
         put(&sc.vol, sizeof(fdk_volume));
         put(&sc.proj.n_proj, 4 * sizeof(int32_t));
         put(&sc.proj.data, sizeof(void*));
@@ -790,8 +804,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         const int i = order[j];
         stage_off[j] = stage_total;
         const int es_i = esize_of(scans[i].proj.dtype);
-        stage_total += staged_bytes(&scans[i].proj, es_i,
-                                    batched_layout(fit_layout(pick_tile(maxL, scans[i].proj.dtype), &scans[i].proj, es_i).layout));
+        stage_total += staged_bytes(&scans[i].proj, es_i, scan_layout(&scans[i].proj));
     }
 
     if ((st = begin_call(*d, s)) != FDK_OK) return st;
@@ -799,9 +812,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         // growing the staging buffer invalidates every captured graph
         HIP_TRY(hipDeviceSynchronize());
         for (BatchEntry& b : d->batch_cache) {
-            if (b.exec) (void)hipGraphExecDestroy(b.exec);
-            release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
-            release(b.coef64); release(b.coef_dev); release(b.counter);
+            release_entry(b);
         }
         d->batch_cache.clear();
         hipError_t e = ensure(d->batch_staged, stage_total);
@@ -820,9 +831,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         if (d->batch_cache.size() >= kBatchCacheMax) {
             HIP_TRY(hipDeviceSynchronize());
             BatchEntry& b = d->batch_cache.back();
-            if (b.exec) (void)hipGraphExecDestroy(b.exec);
-            release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
-            release(b.coef64); release(b.coef_dev); release(b.counter);
+            release_entry(b);
             d->batch_cache.pop_back();
         }
         // host tables
@@ -837,6 +846,8 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         std::vector<int32_t> item_begin(n_scans + 1);
         std::vector<float> out_scales(n_scans);
         std::vector<int> proj_begin(n_scans);
+        std::vector<int64_t> win_off(n_scans);   // window table offset (layout 3) or -1
+        uint64_t win_total = 0;
         int64_t rows = 0;
         int64_t items = 0;
         for (int j = 0; j < n_scans; ++j) {
@@ -852,12 +863,15 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
             out_scales[j] = c.out_scale;
             const int es = esize_of(sc.proj.dtype);
             TileShape ts = t;
-            ts.layout = batched_layout(fit_layout(pick_tile(maxL, sc.proj.dtype), &sc.proj, es).layout);
+            ts.layout = scan_layout(&sc.proj);
             stages[j] = make_stage(&sc.proj, es, ts.layout, static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j], rows);
             rows += (int64_t)sc.proj.n_proj * stages[j].Hp;
             item_begin[j] = (int32_t)items;
             TileArgs probe = make_args(&sc.vol, &sc.proj, es, ts, nullptr, nullptr, nullptr, 1.0f, 0, sc.proj.dtype);
-            items += (int64_t)probe.tiles_x * probe.tiles_y * probe.tiles_z;
+            const int64_t n_tiles = (int64_t)probe.tiles_x * probe.tiles_y * probe.tiles_z;
+            win_off[j] = ts.layout == 3 ? win_total : -1;
+            if (ts.layout == 3) win_total += (uint64_t)n_tiles * sc.proj.n_proj;
+            items += n_tiles;
             if (items > 0x7fffffffLL) return fail(FDK_E_INVALID_ARG, "batch too large for one launch");
         }
         item_begin[n_scans] = (int32_t)items;
@@ -874,19 +888,20 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         alloc(b.coef64, coef64.size() * sizeof(double));
         alloc(b.coef_dev, (size_t)total_proj * 16 * sizeof(double));
         alloc(b.counter, sizeof(unsigned));
+        if (win_total > 0) alloc(b.windows, win_total * sizeof(Win));
         if (e != hipSuccess) {
-            release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
-            release(b.coef64); release(b.coef_dev); release(b.counter);
+            release_entry(b);
             return fail(FDK_E_NOMEM, "batched tables: %s", hipGetErrorString(e));
         }
         for (int j = 0; j < n_scans; ++j) {
             const fdk_scan& sc = scans[order[j]];
             TileShape ts = t;
-            ts.layout = batched_layout(fit_layout(pick_tile(maxL, sc.proj.dtype), &sc.proj, esize_of(sc.proj.dtype)).layout);
+            ts.layout = scan_layout(&sc.proj);
             tiles[j] = make_args(&sc.vol, &sc.proj, esize_of(sc.proj.dtype), ts,
                                  static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j],
                                  static_cast<double*>(b.coef_dev.p) + (size_t)proj_begin[j] * 16, sc.volume,
                                  out_scales[j], accumulate, sc.proj.dtype);
+            if (win_off[j] >= 0) tiles[j].win = static_cast<const Win*>(b.windows.p) + win_off[j];
         }
         auto up = [&](DevBuf& buf, const void* src, size_t n) {
             if (e == hipSuccess) e = hipMemcpyAsync(buf.p, src, n, hipMemcpyHostToDevice, s);
@@ -910,6 +925,13 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
             hipError_t e2 = launch_fold(static_cast<const double*>(b.coef64.p),
                                         static_cast<const float* const*>(b.scale_ptrs.p),
                                         static_cast<double*>(b.coef_dev.p), total_proj, d->capture_stream);
+            // window tables of the scans that sample from LDS (needs the folded coefficients)
+            hipError_t ew = hipSuccess;
+            for (int j = 0; j < n_scans && ew == hipSuccess; ++j)
+                if (win_off[j] >= 0)
+                    ew = launch_window(tiles[j], t.strip, t.waves,
+                                       static_cast<Win*>(b.windows.p) + win_off[j], d->capture_stream);
+            if (e2 == hipSuccess) e2 = ew;
             hipError_t e3 = launch_reset_counter(static_cast<unsigned*>(b.counter.p), d->capture_stream);
             hipError_t e4 = launch_bp_batched(static_cast<const TileArgs*>(b.tiles.p),
                                               static_cast<const int32_t*>(b.item_begin.p), n_scans,
@@ -921,9 +943,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         if (e == hipSuccess) e = hipGraphInstantiate(&b.exec, graph, nullptr, nullptr, 0);
         if (graph != nullptr) (void)hipGraphDestroy(graph);
         if (e != hipSuccess) {
-            if (b.exec) (void)hipGraphExecDestroy(b.exec);
-            release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
-            release(b.coef64); release(b.coef_dev); release(b.counter);
+            release_entry(b);
             return fail(FDK_E_DEVICE, "batched graph build failed: %s", hipGetErrorString(e));
         }
         d->batch_cache.push_front(std::move(b));
@@ -939,7 +959,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
 fdk_status fdk_set_tile(int32_t dtype, int32_t strip, int32_t waves, int32_t layout)
 {
     g_last_error.clear();
-    if (dtype < 0 || dtype > kAdjointSlot) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
+    if (dtype < 0 || dtype >= kSlots) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
     std::lock_guard<std::mutex> lock(g_mu);
     if (strip == 0 && waves == 0) {
         g_tune.forced[dtype] = {0, 0, 0};
@@ -958,7 +978,7 @@ fdk_status fdk_get_tile(const fdk_volume* vol, int32_t dtype, int32_t* strip, in
     g_last_error.clear();
     fdk_status st = check_volume(vol);
     if (st != FDK_OK) return st;
-    if (dtype < 0 || dtype > kAdjointSlot) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
+    if (dtype < 0 || dtype >= kSlots) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
     if (strip == nullptr || waves == nullptr || layout == nullptr) return fail(FDK_E_INVALID_ARG, "NULL output");
     std::lock_guard<std::mutex> lock(g_mu);
     load_env_tuning();
@@ -973,7 +993,7 @@ fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip
                                 int32_t layout)
 {
     g_last_error.clear();
-    if (dtype < 0 || dtype > kAdjointSlot) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
+    if (dtype < 0 || dtype >= kSlots) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
     if (size_class < 0 || size_class > 15) return fail(FDK_E_INVALID_ARG, "size class %d", size_class);
     std::lock_guard<std::mutex> lock(g_mu);
     if (strip == 0 && waves == 0) {
@@ -1014,7 +1034,7 @@ int32_t fdk_load_tuning(const char* path)
         }
         int dt, cls, s, w, lay;
         if (std::sscanf(line, "%d %d %d %d %d", &dt, &cls, &s, &w, &lay) == 5) {
-            if (dt < 0 || dt > kAdjointSlot || cls < 0 || cls > 15 || !valid_shape(dt, TileShape{s, w, lay})) {
+            if (dt < 0 || dt >= kSlots || cls < 0 || cls > 15 || !valid_shape(dt, TileShape{s, w, lay})) {
                 std::fclose(f);
                 return fail(FDK_E_INVALID_ARG, "%s: bad entry '%d %d %d %d %d'", path, dt, cls, s, w, lay);
             }
@@ -1046,9 +1066,7 @@ fdk_status fdk_release_workspace(void)
     for (CoefEntry& c : d.coef_cache) release(c.buf);
     d.coef_cache.clear();
     for (BatchEntry& b : d.batch_cache) {
-        if (b.exec) (void)hipGraphExecDestroy(b.exec);
-        release(b.tiles); release(b.item_begin); release(b.stage); release(b.scale_ptrs);
-        release(b.coef64); release(b.coef_dev); release(b.counter);
+        release_entry(b);
     }
     d.batch_cache.clear();
     release(d.batch_staged);

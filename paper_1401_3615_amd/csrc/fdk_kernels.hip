@@ -634,12 +634,10 @@ __device__ __forceinline__ void window_store(float* lds, const float4 (&pre)[kPr
     }
 }
 
+// One tile of the LDS backprojection; `lds` is the workgroup's 32 KiB tile.
 template <typename T, int S, int NW>
-__global__ __launch_bounds__(kWave * NW)
-    __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<S, NW>(), lds_waves_per_eu<S, NW>()))) void bp_lds_kernel(TileArgs a)
+__device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot_div, float* lds)
 {
-    __shared__ __attribute__((aligned(16))) float lds[kLdsCap];
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const TilePos p = tile_pos<S, NW>(a, tile);
     float acc[S];
 #pragma unroll
@@ -647,7 +645,7 @@ __global__ __launch_bounds__(kWave * NW)
     const uint32_t row = a.row_bytes;
     const int wp = (int)(a.row_bytes / sizeof(T));
     const Win* wins = a.win + (int64_t)tile * a.n_proj;
-    ProjOrder po(a, tile, a.rot_div);
+    ProjOrder po(a, tile, rot_div);
     Coef next = load_coef(a.coef, po.k);
     // software pipeline: the window of the projection after this one is
     // loaded into registers while this one is sampled from LDS
@@ -735,18 +733,27 @@ __global__ __launch_bounds__(kWave * NW)
     }
 }
 
+template <typename T, int S, int NW>
+__global__ __launch_bounds__(kWave * NW)
+    __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<S, NW>(), lds_waves_per_eu<S, NW>()))) void bp_lds_kernel(TileArgs a)
+{
+    __shared__ __attribute__((aligned(16))) float lds[kLdsCap];
+    bp_lds_tile<T, S, NW>(a, xcd_remap(blockIdx.x, gridDim.x), a.rot_div, lds);
+}
+
 // Persistent backprojection over many scans: every workgroup pulls
 // (scan, tile) items from a queue until it is empty.  Items are ordered by
 // decreasing cost (projection count) on the host, so the tail is made of the
 // cheapest tiles.
 template <int S, int NW>
 __global__ __launch_bounds__(kWave * NW)
-    __attribute__((amdgpu_waves_per_eu(waves_per_eu<S>(), waves_per_eu<S>()))) void bp_batched_kernel(const TileArgs* __restrict__ scans,
+    __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<S, NW>(), lds_waves_per_eu<S, NW>()))) void bp_batched_kernel(const TileArgs* __restrict__ scans,
                                                                 const int32_t* __restrict__ item_begin,
                                                                 int n_scans, unsigned* counter,
                                                                 int total_items)
 {
     __shared__ int s_item;
+    __shared__ __attribute__((aligned(16))) float lds[kLdsCap];
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
         __syncthreads();
@@ -760,7 +767,13 @@ __global__ __launch_bounds__(kWave * NW)
         }
         const TileArgs a = scans[lo];
         const int tile = item - item_begin[lo];
-        bp_tile_any<S, NW>(a, tile, (int)gridDim.x);
+        if (a.layout == 3) {
+            if (a.dtype == 1) bp_lds_tile<__half, S, NW>(a, tile, (int)gridDim.x, lds);
+            else if (a.dtype == 2) bp_lds_tile<bf16_t, S, NW>(a, tile, (int)gridDim.x, lds);
+            else bp_lds_tile<float, S, NW>(a, tile, (int)gridDim.x, lds);
+        } else {
+            bp_tile_any<S, NW>(a, tile, (int)gridDim.x);
+        }
     }
 }
 

@@ -187,8 +187,44 @@ def test_adjoint_tiles(fdk):
     assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == (16, 1, 4)
 
 
+def test_batched_slot(fdk):
+    vol = fdk.Volume(256, 1.0)
+    assert fdk.get_tile(vol, fdk.TUNE_BATCHED) == fdk.get_tile(vol, fdk.F32)   # default follows FP32
+    fdk.set_tile(fdk.TUNE_BATCHED, 8, 2, 1)
+    try:
+        assert fdk.get_tile(vol, fdk.TUNE_BATCHED) == (8, 2, 1)
+        with pytest.raises(fdk.FdkError):
+            fdk.set_tile(fdk.TUNE_BATCHED, 8, 2, 4)
+    finally:
+        fdk.set_tile(fdk.TUNE_BATCHED, 0, 0)
+    with pytest.raises(fdk.FdkError):
+        fdk.set_tile(5, 8, 2, 0)   # no such slot
+
+
 def test_header_struct_layout(fdk):
     """The ctypes mirror has the sizes the C structs have."""
     assert ctypes.sizeof(fdk._Volume) == 48
     assert ctypes.sizeof(fdk._Proj) == 40
     assert ctypes.sizeof(fdk._Scan) == 96
+
+
+def test_autotune_file_round_trip(fdk, tmp_path):
+    """The autotuner's writer produces a file the library's loader accepts."""
+    from paper_1401_3615_amd import autotune
+    res = [autotune.Result(0, 9, 16, 4, 3, 1000.0), autotune.Result(1, 8, 8, 2, 1, 900.0),
+           autotune.Result(3, 8, 16, 2, 4, 400.0)]
+    path = tmp_path / "tuned.txt"
+    autotune.write(res, str(path))
+    assert path.read_text().startswith(f"fdk-tuning {fdk.abi_version()} gfx950\n")
+    try:
+        assert fdk.load_tuning(str(path)) == 3
+        assert fdk.get_tile(fdk.Volume(512, 0.5), fdk.F32) == (16, 4, 3)
+        assert fdk.get_tile(fdk.Volume(300, 0.5), fdk.F16) == (8, 2, 1)
+        assert fdk.get_tile(fdk.Volume(256, 0.5), fdk.TUNE_ADJOINT) == (16, 2, 4)
+    finally:
+        for r in res:
+            fdk.set_tuning_entry(r.slot, r.size_class, 0, 0)
+    for slot in (fdk.F32, fdk.F16, fdk.BF16, fdk.TUNE_ADJOINT):
+        for strip, waves, layout in autotune.candidates(slot):
+            fdk.set_tile(slot, strip, waves, layout)   # every candidate is a compiled shape
+        fdk.set_tile(slot, 0, 0)

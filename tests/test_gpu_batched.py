@@ -45,11 +45,11 @@ SPECS = [(37, 3.0, 9, 101, 77, 20), (64, 1.5, 17, 160, 128, 21), (24, 4.0, 5, 96
 def test_batched_matches_single_and_oracle(fdk):
     dts = [torch.float32, torch.float16, torch.float32, torch.bfloat16, torch.float32]
     scans, host = make_scans(fdk, SPECS, dts)
-    # the batched launch uses one tile shape for all scans; pin it for the single calls
+    # the batched launch uses one tile shape for all scans (the batched slot;
+    # FP16/BF16 scans keep their own slot's layout); pin it for the single calls
     maxvol = fdk.Volume(max(sp[0] for sp in SPECS), 1.0)
-    s, w, _ = fdk.get_tile(maxvol, fdk.F32)
-    # the persistent kernel gathers from staged images (LDS tiles, layout 3, map to layout 0)
-    lays = {dt: (lambda l: 0 if l == 3 else l)(fdk.get_tile(maxvol, dt)[2]) for dt in (fdk.F32, fdk.F16, fdk.BF16)}
+    s, w, lay32 = fdk.get_tile(maxvol, fdk.TUNE_BATCHED)
+    lays = {fdk.F32: lay32, fdk.F16: fdk.get_tile(maxvol, fdk.F16)[2], fdk.BF16: fdk.get_tile(maxvol, fdk.BF16)[2]}
     fdk.backproject_batched(scans)
     torch.cuda.synchronize()
     for dt in (fdk.F32, fdk.F16, fdk.BF16):
@@ -119,3 +119,42 @@ def test_batched_every_item_once(fdk):
     for s, (L, voxel, N, W, H, seed) in zip(scans, specs):
         ref = oracle.backproject(L, voxel, s.geom.mats, np.ones((N, H, W), np.float32))
         assert_parity(s.out.cpu().numpy(), ref, what=f"tiny scan L={L} N={N}")
+
+
+def test_autotuner_on_device(fdk, tmp_path):
+    """A short tuning run picks valid shapes whose calls still match the oracle."""
+    from paper_1401_3615_amd import autotune
+    geom = autotune.carm_geometry(12, 256, 200, 1.5)
+    res = autotune.tune(geom, [40], slots=(fdk.F32, fdk.TUNE_ADJOINT), reps=1)
+    assert {r.slot for r in res} == {fdk.F32, fdk.TUNE_ADJOINT}
+    path = tmp_path / "t.txt"
+    autotune.write(res, str(path))
+    try:
+        assert fdk.load_tuning(str(path)) == 2
+        vol = fdk.Volume(40, 0.5 * 512 / 40)
+        r32 = [r for r in res if r.slot == fdk.F32][0]
+        assert fdk.get_tile(vol, fdk.F32) == (r32.strip, r32.waves, r32.layout)
+        q = torch.randn(12, 200, 256, generator=torch.Generator().manual_seed(3))
+        out = fdk.backproject(q.to(DEV), geom, vol)
+        torch.cuda.synchronize()
+        ref = oracle.backproject(40, vol.voxel_mm, geom.mats, q.numpy())
+        assert_parity(out.cpu().numpy(), ref, what="tuned shape")
+    finally:
+        for r in res:
+            fdk.set_tuning_entry(r.slot, r.size_class, 0, 0)
+
+
+@pytest.mark.parametrize("layout", [0, 1, 3])
+def test_batched_layouts(fdk, layout):
+    """The persistent kernel with FP32 scans gathering from plain or quad
+    staged images, or sampling LDS windows."""
+    scans, host = make_scans(fdk, SPECS, [torch.float32] * len(SPECS))
+    fdk.set_tile(fdk.TUNE_BATCHED, 8, 4, layout)
+    try:
+        fdk.backproject_batched(scans)
+        torch.cuda.synchronize()
+    finally:
+        fdk.set_tile(fdk.TUNE_BATCHED, 0, 0)
+    for sc, (L, voxel, mats, q, qd, scale) in zip(scans, host):
+        ref = oracle.backproject(L, voxel, mats, q.numpy())
+        assert_parity(sc.out.cpu().numpy(), ref, what=f"batched layout {layout} L={L}")

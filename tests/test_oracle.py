@@ -295,3 +295,22 @@ def test_matrix_layout_listing_form():
     v = X[0] * A_cm[1] + X[1] * A_cm[4] + X[2] * A_cm[7] + A_cm[10]
     w = X[0] * A_cm[2] + X[1] * A_cm[5] + X[2] * A_cm[8] + A_cm[11]
     np.testing.assert_allclose(P @ np.append(X, 1.0), [u, v, w], rtol=1e-14)
+
+
+def test_supported_update_count_matches_paper_workload():
+    """The stored supported-update count of the synthetic 512^3 x 496 C-arm
+    workload (written by tests/golden/make_supported_updates.py with the
+    oracle) is within 2% of the clipped update count the paper derives for the
+    RabbitCT scan (4.39e10, Sec. "Performance Model"), and consistent with the
+    oracle's counter on a slab of planes."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "supported_updates.json")) as f:
+        rec = json.load(f)["512^3 @0.5mm x 496 x 1248x960, 200deg C-arm"]
+    assert rec["nominal"] == 512 ** 3 * 496
+    assert abs(rec["supported"] / 4.39e10 - 1.0) < 0.02
+    # the oracle's counter on a slab stays within that slab's nominal count
+    carm = S.CArm(8)
+    mats = S.carm_matrices(carm)
+    n = oracle.supported_updates(64, 0.5 * 512 / 64, mats, carm.width, carm.height, z_range=(30, 4))
+    assert 0 < n <= 64 * 64 * 4 * 8
