@@ -40,11 +40,15 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def bp_kernel_name(fdk, vol) -> str:
-    """Name of the FP32 backprojection kernel the library launches for `vol`."""
+def bp_kernel_name(fdk, vol, mats) -> str:
+    """Name of the FP32 backprojection kernel the library launches for `vol`
+    (the LDS kernel is instantiated for w constant along z, i.e. a zero
+    z-coefficient in every matrix's third row, or not)."""
+    import numpy as np
     strip, waves, layout = fdk.get_tile(vol, fdk.F32)
     if layout == 3:
-        return f"bp_lds_kernel<float, {strip}, {waves}>"
+        cw = int(bool(np.all(np.asarray(mats)[:, 2, 2] == 0.0)))
+        return f"bp_lds_kernel<float, {strip}, {waves}, {cw}>"
     return f"bp_kernel<float, {layout}, {strip}, {waves}>"
 
 
@@ -148,13 +152,13 @@ def main() -> int:
     if args.profile_only:
         # calibration for HBM counters: an elementwise kernel that reads and
         # writes COPY_BYTES each
-        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(2):
-            torch.mul(src, 2.0, out=dst)
+            torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
         print(json.dumps({"metric": "fp32_gups", "value": value, "ms_per_step": ms,
-                          "kernel": bp_kernel_name(fdk, vol), "copy_bytes_each_way": COPY_BYTES}), flush=True)
+                          "kernel": bp_kernel_name(fdk, vol, mats), "copy_bytes_each_way": COPY_BYTES}), flush=True)
         return 0
     vol32 = out.clone()
 
@@ -258,7 +262,7 @@ def main() -> int:
             traffic = cnt["hbm_bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "kernel": bp_kernel_name(fdk, vol), "kernel_ms": round(bp_kernel_ms, 3),
+                "kernel": bp_kernel_name(fdk, vol, mats), "kernel_ms": round(bp_kernel_ms, 3),
                 "flop_per_update": FLOP_PER_UPDATE,
                 "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED, 4)}
 

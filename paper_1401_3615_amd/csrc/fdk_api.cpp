@@ -126,6 +126,7 @@ fdk_status check_geometry(const fdk_volume* v, const fdk_projections* p)
 struct Composed {
     std::vector<double> coef;  // n_proj * 12
     float out_scale;
+    bool const_w;              // w independent of z for every projection (coefficient exactly 0)
 };
 
 Composed compose(const fdk_volume* v, const fdk_projections* p)
@@ -160,6 +161,8 @@ Composed compose(const fdk_volume* v, const fdk_projections* p)
     const double s = std::ldexp(1.0, e);
     for (double& x : c.coef) x *= s;
     c.out_scale = (float)std::ldexp(1.0, 2 * e);
+    c.const_w = true;
+    for (int k = 0; k < N; ++k) c.const_w = c.const_w && c.coef[(size_t)k * 12 + 10] == 0.0;
     return c;
 }
 
@@ -294,6 +297,7 @@ struct CoefEntry {
     std::string key;
     DevBuf buf;
     float out_scale;
+    bool const_w;
 };
 
 struct BatchEntry {
@@ -386,7 +390,7 @@ std::string coef_key(const fdk_volume* v, const fdk_projections* p)
 
 // Device copy of the composed FP64 coefficients, cached by geometry content.
 fdk_status coef_table(DeviceState& d, const fdk_volume* v, const fdk_projections* p, hipStream_t s,
-                      const double** dev, float* out_scale)
+                      const double** dev, float* out_scale, int* const_w = nullptr)
 {
     std::string key = coef_key(v, p);
     for (auto it = d.coef_cache.begin(); it != d.coef_cache.end(); ++it) {
@@ -394,6 +398,7 @@ fdk_status coef_table(DeviceState& d, const fdk_volume* v, const fdk_projections
             d.coef_cache.splice(d.coef_cache.begin(), d.coef_cache, it);
             *dev = static_cast<const double*>(d.coef_cache.front().buf.p);
             *out_scale = d.coef_cache.front().out_scale;
+            if (const_w) *const_w = d.coef_cache.front().const_w;
             return FDK_OK;
         }
     }
@@ -409,6 +414,7 @@ fdk_status coef_table(DeviceState& d, const fdk_volume* v, const fdk_projections
     CoefEntry e;
     e.key = std::move(key);
     e.out_scale = c.out_scale;
+    e.const_w = c.const_w;
     hipError_t err = ensure(e.buf, c.coef.size() * sizeof(double));
     if (err != hipSuccess) return fail(FDK_E_NOMEM, "coefficient table allocation failed: %s", hipGetErrorString(err));
     err = hipMemcpyAsync(e.buf.p, c.coef.data(), c.coef.size() * sizeof(double), hipMemcpyHostToDevice, s);
@@ -420,6 +426,7 @@ fdk_status coef_table(DeviceState& d, const fdk_volume* v, const fdk_projections
     d.coef_cache.push_front(std::move(e));
     *dev = static_cast<const double*>(d.coef_cache.front().buf.p);
     *out_scale = d.coef_cache.front().out_scale;
+    if (const_w) *const_w = d.coef_cache.front().const_w;
     return FDK_OK;
 }
 
@@ -500,6 +507,7 @@ TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, Til
     a.cv = cv;
     a.win = nullptr;
     a.rot_div = 0;
+    a.const_w = 0;
     return a;
 }
 
@@ -599,7 +607,8 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "coefficient workspace: %s", hipGetErrorString(e));
     const double* coef64 = nullptr;
     float out_scale = 1.0f;
-    if ((st = coef_table(*d, vol, proj, s, &coef64, &out_scale)) != FDK_OK) return st;
+    int const_w = 0;
+    if ((st = coef_table(*d, vol, proj, s, &coef64, &out_scale, &const_w)) != FDK_OK) return st;
 
     StageArgs sa = make_stage(proj, es, t.layout, static_cast<unsigned char*>(d->staged.p), 0);
     {
@@ -612,6 +621,7 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     }
     TileArgs a = make_args(vol, proj, es, t, static_cast<unsigned char*>(d->staged.p),
                            static_cast<double*>(d->coef_dev.p), volume, out_scale, accumulate, proj->dtype);
+    a.const_w = const_w;
     if (t.layout == 3) {
         const uint64_t nwin = (uint64_t)a.tiles_x * a.tiles_y * a.tiles_z * proj->n_proj;
         e = ensure(d->windows, nwin * sizeof(Win));
@@ -649,11 +659,13 @@ static fdk_status forwardproject_tiles(const fdk_volume* vol, const float* volum
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "coefficient workspace: %s", hipGetErrorString(e));
     const double* coef64 = nullptr;
     float out_scale = 1.0f;
-    if ((st = coef_table(*d, vol, geom, s, &coef64, &out_scale)) != FDK_OK) return st;
+    int const_w = 0;
+    if ((st = coef_table(*d, vol, geom, s, &coef64, &out_scale, &const_w)) != FDK_OK) return st;
     {
         ProfScope ps("fold", s);
         HIP_TRY(launch_fold_single(coef64, nullptr, static_cast<double*>(d->coef_dev.p), geom->n_proj, s));
     }
+    b.const_w = const_w;
     b.coef = static_cast<const double*>(d->coef_dev.p);
     b.vol = volume;
     b.out = proj_out;

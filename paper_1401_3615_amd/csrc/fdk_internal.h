@@ -49,6 +49,7 @@ struct TileArgs {
     const Win* win;              // layout 3: n_tiles x n_proj windows
     int32_t cu, cv;              // integer detector centre (W/2, H/2)
     int32_t rot_div;             // projection-order rotation divisor (0: every tile starts at k = 0)
+    int32_t const_w;             // 1: w does not depend on z for any projection of the launch
 };
 
 // Forward projection by detector-tile ownership: one workgroup per
@@ -63,6 +64,7 @@ struct BandArgs {
     int32_t tw, th, tiles_u, tiles_v;
     float out_scale;
     int32_t accumulate;
+    int32_t const_w;             // 1: w does not depend on z for any projection
 };
 
 // group = projections per workgroup (1, 2, 4 or 8); P tw th <= kBandCap

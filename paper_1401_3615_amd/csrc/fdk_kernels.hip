@@ -298,8 +298,8 @@ __device__ __forceinline__ bool strip_touches(const Strip& st)
 // w does not change along z (the projection's depth axis is perpendicular to
 // the z axis, dw = 0 exactly, as for a circular orbit about z), 1/w is one
 // reciprocal per strip and the remainders u/w, v/w step linearly: two FMAs per
-// voxel instead of a reciprocal and two multiplies.  The choice is uniform per
-// projection.
+// voxel instead of a reciprocal and two multiplies.  The choice is made per
+// projection (uniform), around the strip loop.
 template <bool CONSTW>
 struct Walk {
     float ax, bx, ay, by, aw, bw, r2;
@@ -340,7 +340,7 @@ struct Walk {
 };
 
 // Runs body(std::true_type) when projection c has w constant along z, else
-// body(std::false_type).
+// body(std::false_type); the condition is uniform per projection.
 template <typename F>
 __device__ __forceinline__ void with_walk(const double* c, F&& body)
 {
@@ -568,7 +568,8 @@ constexpr int kLdsCap = 8192;   // FP32 pixels of the per-workgroup projection t
 template <int S, int NW>
 constexpr int lds_waves_per_eu()
 {
-    return (5 * NW / 4) < 1 ? 1 : ((5 * NW / 4) < waves_per_eu<S>() ? (5 * NW / 4) : waves_per_eu<S>());
+    // five 32 KiB tiles per CU; strips of 32 keep more accumulators and fit three
+    return (5 * NW / 4) < 1 ? 1 : ((5 * NW / 4) < (S <= 16 ? 5 : 3) ? (5 * NW / 4) : (S <= 16 ? 5 : 3));
 }
 
 // The window of one projection as the LDS tile holds it: 4-pixel chunks
@@ -593,49 +594,66 @@ struct LdsWin {
 
 // Chunks of a window prefetched into registers per thread while the previous
 // projection is sampled (kPre x 256 threads x 4 pixels = 4096 pixels for a
-// 4-wave workgroup); larger windows load their remainder after the barrier.
+// 4-wave workgroup), with the LDS offset each one goes to; larger windows
+// load their remainder after the barrier.
 constexpr int kPre = 4;
 
+struct Fill {
+    float4 v[kPre];
+    int lo[kPre];   // LDS float offset of chunk i of this thread, -1 if it has none
+};
+
 template <typename T, int NW>
-__device__ __forceinline__ void window_prefetch(float4 (&pre)[kPre], const LdsWin& w, __amdgpu_buffer_rsrc_t rs,
-                                                int wp)
+__device__ __forceinline__ void window_prefetch(Fill& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs, int wp)
 {
-    const float inv_nc = 1.0f / (float)w.nc;
+    // chunk e = t + i * NT of the window, row-major by 4-pixel chunks: row and
+    // column are found once and then stepped by NT
+    // (e + 0.5) * rcp(nc) floors to e / nc exactly: the relative error of the
+    // product (2 ulp) stays below 0.5 / nc for e, nc < 2^14
+    constexpr int NT = kWave * NW;
+    const float inv_nc = __builtin_amdgcn_rcpf((float)w.nc);
+    const int q = (int)(((float)NT + 0.5f) * inv_nc), rm = NT - __mul24(q, w.nc);
+    int e = (int)threadIdx.x;
+    int r = (int)(((float)e + 0.5f) * inv_nc);
+    int cc = e - __mul24(r, w.nc);
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
-        const int e = (int)threadIdx.x + i * kWave * NW;
+        f.lo[i] = -1;
         if (e < w.total) {
-            const int r = (int)(((float)e + 0.5f) * inv_nc);
-            const int cc = e - r * w.nc;
-            pre[i] = Chunk<T>::load(rs, (uint32_t)((w.j0 + r) * wp + w.c_lo + 4 * cc));
+            f.v[i] = Chunk<T>::load(rs, (uint32_t)(__mul24(w.j0 + r, wp) + w.c_lo + 4 * cc));
+            f.lo[i] = __mul24(r, w.tw) + 4 * cc;
+        }
+        e += NT;
+        r += q;
+        cc += rm;
+        if (cc >= w.nc) {
+            cc -= w.nc;
+            ++r;
         }
     }
 }
 
 template <typename T, int NW>
-__device__ __forceinline__ void window_store(float* lds, const float4 (&pre)[kPre], const LdsWin& w,
-                                             __amdgpu_buffer_rsrc_t rs, int wp)
+__device__ __forceinline__ void window_store(float* lds, const Fill& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs,
+                                             int wp)
 {
-    const float inv_nc = 1.0f / (float)w.nc;
 #pragma unroll
-    for (int i = 0; i < kPre; ++i) {
-        const int e = (int)threadIdx.x + i * kWave * NW;
-        if (e < w.total) {
-            const int r = (int)(((float)e + 0.5f) * inv_nc);
-            const int cc = e - r * w.nc;
-            *reinterpret_cast<float4*>(&lds[r * w.tw + 4 * cc]) = pre[i];
-        }
-    }
+    for (int i = 0; i < kPre; ++i)
+        if (f.lo[i] >= 0) *reinterpret_cast<float4*>(&lds[f.lo[i]]) = f.v[i];
+    const float inv_nc = __builtin_amdgcn_rcpf((float)w.nc);
     for (int e = (int)threadIdx.x + kPre * kWave * NW; e < w.total; e += kWave * NW) {
         const int r = (int)(((float)e + 0.5f) * inv_nc);
-        const int cc = e - r * w.nc;
-        *reinterpret_cast<float4*>(&lds[r * w.tw + 4 * cc]) =
-            Chunk<T>::load(rs, (uint32_t)((w.j0 + r) * wp + w.c_lo + 4 * cc));
+        const int cc = e - __mul24(r, w.nc);
+        *reinterpret_cast<float4*>(&lds[__mul24(r, w.tw) + 4 * cc]) =
+            Chunk<T>::load(rs, (uint32_t)(__mul24(w.j0 + r, wp) + w.c_lo + 4 * cc));
     }
 }
 
 // One tile of the LDS backprojection; `lds` is the workgroup's 32 KiB tile.
-template <typename T, int S, int NW>
+// CWM: 1 every projection has w constant along z (one 1/w per strip), 0 none
+// is assumed to, 2 decided per projection (the persistent kernel, whose scans
+// differ).
+template <typename T, int S, int NW, int CWM>
 __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot_div, float* lds)
 {
     const TilePos p = tile_pos<S, NW>(a, tile);
@@ -646,18 +664,17 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     const int wp = (int)(a.row_bytes / sizeof(T));
     const Win* wins = a.win + (int64_t)tile * a.n_proj;
     ProjOrder po(a, tile, rot_div);
-    Coef next = load_coef(a.coef, po.k);
     // software pipeline: the window of the projection after this one is
     // loaded into registers while this one is sampled from LDS
-    float4 pre[kPre];
+    Fill pre;
     LdsWin wv(wins[po.k]);
+    bool big = false;
     if (wv.fits) window_prefetch<T, NW>(pre, wv, make_rsrc(po.img, a.proj_bytes), wp);
     for (int n = 0; n < a.n_proj; ++n) {
-        const Coef cur = next;
+        const Coef cur = load_coef(a.coef, po.k);
         const unsigned char* img = po.img;
         po.advance(a);
         const bool more = n + 1 < a.n_proj;
-        if (more) next = load_coef(a.coef, po.k);
         const LdsWin wn(more ? wins[po.k] : Win{1, 0, 1, 0});
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
         const __amdgpu_buffer_rsrc_t rs_next = make_rsrc(po.img, a.proj_bytes);
@@ -665,16 +682,18 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
             __syncthreads();                                // previous projection's reads are done
             window_store<T, NW>(lds, pre, wv, rs, wp);
             __syncthreads();
-            if (wn.fits) window_prefetch<T, NW>(pre, wn, rs_next, wp);
+        }
+        if (wn.fits) window_prefetch<T, NW>(pre, wn, rs_next, wp);
+        if (wv.fits) {
             const Strip st = strip_setup<2>(cur.c, p, a, wp);
             // anchor in staged-pixel coordinates; clamp so both tap columns
             // and rows stay inside the window held in LDS
             const float ax = st.fau + (float)(a.cu + kPadLo), ay = st.fav + (float)(a.cv + kPadLo);
             const float lox = (float)wv.c_lo - ax, hix = (float)(wv.c_hi - 1) - ax;
             const float loy = (float)wv.j0 - ay, hiy = (float)(wv.j1 - 1) - ay;
-            const int base = (((int)ay - wv.j0) * wv.tw + ((int)ax - wv.c_lo)) * 4;
+            const int base = (__mul24((int)ay - wv.j0, wv.tw) + ((int)ax - wv.c_lo)) * 4;
             const uint32_t row_l = (uint32_t)wv.tw * 4;
-            with_walk(cur.c, [&](auto cw) {
+            auto sample = [&](auto cw) {
                 const Walk<decltype(cw)::value> wk(st);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
@@ -693,31 +712,39 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
                     const float val = fmaf(sy, bot - top, top);
                     acc[s] = fmaf(val, wgt, acc[s]);
                 }
-            });
-        } else {
-            if (wn.fits) window_prefetch<T, NW>(pre, wn, rs_next, wp);
-            if (!wv.empty) {
-                // window larger than the LDS tile: gather from the staged image
-                const Strip st = strip_setup<Sampler<T, 0>::kShift>(cur.c, p, a, wp);
+            };
+            if (CWM == 2) with_walk(cur.c, sample);
+            else sample(std::integral_constant<bool, CWM == 1>{});
+        }
+        big |= !wv.fits && !wv.empty;
+        wv = wn;
+    }
+    if (big) {
+        // projections whose window is larger than the LDS tile: gather from
+        // the staged images (kept out of the main loop, which then has a
+        // single sampling path)
+        for (int k = 0; k < a.n_proj; ++k) {
+            const LdsWin w(wins[k]);
+            if (w.fits || w.empty) continue;
+            const Coef cur = load_coef(a.coef, k);
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.proj + (uint64_t)k * a.proj_stride, a.proj_bytes);
+            const Strip st = strip_setup<Sampler<T, 0>::kShift>(cur.c, p, a, wp);
 #pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    constexpr int kMid = S / 2;
-                    const float t = (float)(s - kMid);
-                    const float u = fmaf(t, st.du, st.ub);
-                    const float v = fmaf(t, st.dv, st.vb);
-                    const float w = fmaf(t, st.dw, st.wb);
-                    const float r = __builtin_amdgcn_rcpf(w);
-                    const float dx = __builtin_amdgcn_fmed3f(u * r, st.lox, st.hix);
-                    const float dy = __builtin_amdgcn_fmed3f(v * r, st.loy, st.hiy);
-                    const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
-                    const uint32_t off =
-                        tap_offset<Sampler<T, 0>::kShift>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
-                    const float val = Sampler<T, 0>::sample(rs, off, row, sx, sy);
-                    acc[s] = fmaf(val, r * r, acc[s]);
-                }
+            for (int s = 0; s < S; ++s) {
+                constexpr int kMid = S / 2;
+                const float t = (float)(s - kMid);
+                const float u = fmaf(t, st.du, st.ub);
+                const float v = fmaf(t, st.dv, st.vb);
+                const float w = fmaf(t, st.dw, st.wb);
+                const float r = __builtin_amdgcn_rcpf(w);
+                const float dx = __builtin_amdgcn_fmed3f(u * r, st.lox, st.hix);
+                const float dy = __builtin_amdgcn_fmed3f(v * r, st.loy, st.hiy);
+                const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
+                const uint32_t off = tap_offset<Sampler<T, 0>::kShift>(cvt_floor(dx), cvt_floor(dy), wp, st.base);
+                const float val = Sampler<T, 0>::sample(rs, off, row, sx, sy);
+                acc[s] = fmaf(val, r * r, acc[s]);
             }
         }
-        wv = wn;
     }
     if (p.x < a.L && p.y < a.L) {
         const int64_t plane = (int64_t)a.L * a.L;
@@ -733,12 +760,12 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     }
 }
 
-template <typename T, int S, int NW>
+template <typename T, int S, int NW, int CWM>
 __global__ __launch_bounds__(kWave * NW)
     __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<S, NW>(), lds_waves_per_eu<S, NW>()))) void bp_lds_kernel(TileArgs a)
 {
     __shared__ __attribute__((aligned(16))) float lds[kLdsCap];
-    bp_lds_tile<T, S, NW>(a, xcd_remap(blockIdx.x, gridDim.x), a.rot_div, lds);
+    bp_lds_tile<T, S, NW, CWM>(a, xcd_remap(blockIdx.x, gridDim.x), a.rot_div, lds);
 }
 
 // Persistent backprojection over many scans: every workgroup pulls
@@ -768,9 +795,9 @@ __global__ __launch_bounds__(kWave * NW)
         const TileArgs a = scans[lo];
         const int tile = item - item_begin[lo];
         if (a.layout == 3) {
-            if (a.dtype == 1) bp_lds_tile<__half, S, NW>(a, tile, (int)gridDim.x, lds);
-            else if (a.dtype == 2) bp_lds_tile<bf16_t, S, NW>(a, tile, (int)gridDim.x, lds);
-            else bp_lds_tile<float, S, NW>(a, tile, (int)gridDim.x, lds);
+            if (a.dtype == 1) bp_lds_tile<__half, S, NW, 2>(a, tile, (int)gridDim.x, lds);
+            else if (a.dtype == 2) bp_lds_tile<bf16_t, S, NW, 2>(a, tile, (int)gridDim.x, lds);
+            else bp_lds_tile<float, S, NW, 2>(a, tile, (int)gridDim.x, lds);
         } else {
             bp_tile_any<S, NW>(a, tile, (int)gridDim.x);
         }
@@ -897,7 +924,9 @@ __device__ __forceinline__ BandCol band_interval(float u0, float v0, float w0, f
     return r;
 }
 
-template <int P>
+// CW: w does not change along z for any projection (one 1/w per column and
+// projection; the remainders step linearly).
+template <int P, bool CW>
 __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
 {
     extern __shared__ double lds[];   // P tiles of tw x th, FP64 accumulators
@@ -972,6 +1001,13 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
             swb[p] = wf;
             sdu[p] = (float)fma(-(double)fau, c[10], c[2]);
             sdv[p] = (float)fma(-(double)fav, c[10], c[6]);
+            if (CW) {   // u/w and v/w themselves step linearly; swb holds 1/w^2
+                sub[p] *= rf;
+                svb[p] *= rf;
+                sdu[p] *= rf;
+                sdv[p] *= rf;
+                swb[p] = rf * rf;
+            }
             // tap (i, j) relative to the tile; an inactive projection gets a
             // row offset that keeps every tap outside
             oi[p] = (int)fau + b.cu - i0;
@@ -986,18 +1022,26 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const double* c = coef + 16 * p;
-                const float u = fmaf(t, sdu[p], sub[p]), v = fmaf(t, sdv[p], svb[p]);
-                const float w = fmaf(t, (float)c[10], swb[p]);
-                const float r = __builtin_amdgcn_rcpf(w);
-                const float dx = __builtin_amdgcn_fmed3f(u * r, -2.0e6f, 2.0e6f);
-                const float dy = __builtin_amdgcn_fmed3f(v * r, -2.0e6f, 2.0e6f);
+                float ux, uy, wgt;
+                if (CW) {
+                    ux = fmaf(t, sdu[p], sub[p]);
+                    uy = fmaf(t, sdv[p], svb[p]);
+                    wgt = swb[p];
+                } else {
+                    const float r = __builtin_amdgcn_rcpf(fmaf(t, (float)c[10], swb[p]));
+                    ux = fmaf(t, sdu[p], sub[p]) * r;
+                    uy = fmaf(t, sdv[p], svb[p]) * r;
+                    wgt = r * r;
+                }
+                const float dx = __builtin_amdgcn_fmed3f(ux, -2.0e6f, 2.0e6f);
+                const float dy = __builtin_amdgcn_fmed3f(uy, -2.0e6f, 2.0e6f);
                 const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
                 const int ti = oi[p] + cvt_floor(dx), tj = oj[p] + cvt_floor(dy);
-                const float val = vs * (r * r);
+                const float val = vs * wgt;
                 const float bw = val * sy, tp = val - bw;
                 const bool c0 = (unsigned)ti < (unsigned)tw, c1 = (unsigned)(ti + 1) < (unsigned)tw;
                 const bool r0 = (unsigned)tj < (unsigned)th, r1 = (unsigned)(tj + 1) < (unsigned)th;
-                double* tl = lds + p * tpx + tj * tw + ti;
+                double* tl = lds + p * tpx + __mul24(tj, tw) + ti;
                 if (r0 && c0) __hip_atomic_fetch_add(tl, (double)(tp - tp * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (r0 && c1) __hip_atomic_fetch_add(tl + 1, (double)(tp * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (r1 && c0) __hip_atomic_fetch_add(tl + tw, (double)(bw - bw * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1260,11 +1304,14 @@ hipError_t bp_dispatch_t(const TileArgs& a, int nblocks, hipStream_t st)
     dim3 grid(nblocks), block(kWave * NW);
     if (a.layout == 3) {
         if (a.dtype == 1)
-            launch_rotated(bp_lds_kernel<__half, S, NW>, a, grid, block, st);
+            a.const_w ? launch_rotated(bp_lds_kernel<__half, S, NW, 1>, a, grid, block, st)
+                      : launch_rotated(bp_lds_kernel<__half, S, NW, 0>, a, grid, block, st);
         else if (a.dtype == 2)
-            launch_rotated(bp_lds_kernel<bf16_t, S, NW>, a, grid, block, st);
+            a.const_w ? launch_rotated(bp_lds_kernel<bf16_t, S, NW, 1>, a, grid, block, st)
+                      : launch_rotated(bp_lds_kernel<bf16_t, S, NW, 0>, a, grid, block, st);
         else
-            launch_rotated(bp_lds_kernel<float, S, NW>, a, grid, block, st);
+            a.const_w ? launch_rotated(bp_lds_kernel<float, S, NW, 1>, a, grid, block, st)
+                      : launch_rotated(bp_lds_kernel<float, S, NW, 0>, a, grid, block, st);
         return hipGetLastError();
     }
     if (a.layout == 1)
@@ -1367,7 +1414,7 @@ hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, hipS
 
 int supported_band_group(int p) { return p == 1 || p == 2 || p == 4 || p == 8; }
 
-template <int P>
+template <int P, bool CW>
 static hipError_t launch_band(const BandArgs& b, hipStream_t s)
 {
     const int groups = (b.n_proj + P - 1) / P;
@@ -1376,23 +1423,24 @@ static hipError_t launch_band(const BandArgs& b, hipStream_t s)
     if (blocks > 0x7fffffffLL || lds > (size_t)kBandCap * sizeof(double)) return hipErrorInvalidValue;
     static bool attr_set = false;
     if (!attr_set) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fp_band_kernel<P>),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fp_band_kernel<P, CW>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  kBandCap * (int)sizeof(double));
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(fp_band_kernel<P>, dim3((unsigned)blocks), dim3(kBandThreads), lds, s, b);
+    hipLaunchKernelGGL((fp_band_kernel<P, CW>), dim3((unsigned)blocks), dim3(kBandThreads), lds, s, b);
     return hipGetLastError();
 }
 
 hipError_t launch_fp_band(const BandArgs& b, int group, hipStream_t s)
 {
+    const bool cw = b.const_w != 0;
     switch (group) {
-    case 1: return launch_band<1>(b, s);
-    case 2: return launch_band<2>(b, s);
-    case 4: return launch_band<4>(b, s);
-    case 8: return launch_band<8>(b, s);
+    case 1: return cw ? launch_band<1, true>(b, s) : launch_band<1, false>(b, s);
+    case 2: return cw ? launch_band<2, true>(b, s) : launch_band<2, false>(b, s);
+    case 4: return cw ? launch_band<4, true>(b, s) : launch_band<4, false>(b, s);
+    case 8: return cw ? launch_band<8, true>(b, s) : launch_band<8, false>(b, s);
     default: return hipErrorInvalidValue;
     }
 }
