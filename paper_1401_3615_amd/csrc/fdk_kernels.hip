@@ -210,6 +210,31 @@ template <int NW> struct Patch {
     static constexpr int kBY = NW / kBX;
 };
 
+// Tile order: tiles are numbered block by block, blocks of 8 x 8 x 4 tiles
+// (x fastest inside a block, then y, then z; blocks likewise), edge blocks
+// partial.  Consecutive tiles -- the ones an XCD holds at the same time --
+// then form a compact box of the volume, whose projection footprint is a few
+// hundred kilobytes instead of a band across the whole detector.
+constexpr int kBlkX = 8, kBlkY = 8, kBlkZ = 4;
+
+__device__ __forceinline__ void tile_coords(const TileArgs& a, int tile, int& tx, int& ty, int& tz)
+{
+    const int plane = a.tiles_x * a.tiles_y;
+    const int kz = tile / (plane * kBlkZ);              // z block (all but the last are full)
+    int t = tile - kz * plane * kBlkZ;
+    const int wz = min(kBlkZ, a.tiles_z - kz * kBlkZ);
+    const int jy = t / (a.tiles_x * kBlkY * wz);        // y block row inside the z block
+    t -= jy * a.tiles_x * kBlkY * wz;
+    const int wy = min(kBlkY, a.tiles_y - jy * kBlkY);
+    const int ix = t / (kBlkX * wy * wz);               // x block inside the row
+    t -= ix * kBlkX * wy * wz;
+    const int wx = min(kBlkX, a.tiles_x - ix * kBlkX);
+    const int lx = t % wx, t2 = t / wx;
+    tx = ix * kBlkX + lx;
+    ty = jy * kBlkY + t2 % wy;
+    tz = kz * kBlkZ + t2 / wy;
+}
+
 struct TilePos {
     int x, y, z0;          // column and first plane (buffer-local) of the lane's strip
     double xd, yd, zd;     // centred voxel indices of the strip's anchor voxel
@@ -221,10 +246,8 @@ __device__ __forceinline__ TilePos tile_pos(const TileArgs& a, int tile)
     TilePos p;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    const int tx = tile % a.tiles_x;
-    const int t2 = tile / a.tiles_x;
-    const int ty = t2 % a.tiles_y;
-    const int tz = t2 / a.tiles_y;
+    int tx, ty, tz;
+    tile_coords(a, tile, tx, ty, tz);
     p.x = (tx * Patch<NW>::kBX + wave % Patch<NW>::kBX) * 8 + (lane & 7);
     p.y = (ty * Patch<NW>::kBY + wave / Patch<NW>::kBX) * 8 + (lane >> 3);
     p.z0 = tz * S;
@@ -484,8 +507,8 @@ __global__ void window_kernel(TileArgs a, int strip, int bx, int by, Win* __rest
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles * a.n_proj) return;
     const int tile = (int)(t / a.n_proj), k = (int)(t - (int64_t)tile * a.n_proj);
-    const int tx = tile % a.tiles_x, t2 = tile / a.tiles_x;
-    const int ty = t2 % a.tiles_y, tz = t2 / a.tiles_y;
+    int tx, ty, tz;
+    tile_coords(a, tile, tx, ty, tz);
     const int x0 = tx * 8 * bx, x1 = min(x0 + 8 * bx, a.L) - 1;
     const int y0 = ty * 8 * by, y1 = min(y0 + 8 * by, a.L) - 1;
     const int z0 = tz * strip, z1 = min(z0 + strip, a.z_count) - 1;
