@@ -1,0 +1,301 @@
+// gfx950 kernels around the backprojection: staging of projection stacks
+// into the zero-bordered layouts the backprojection samples (the paper's
+// zero-padding, Sec. "Implementation"), folding of per-projection FP16/BF16
+// scales into the FP64 coefficients, FP16/BF16 packing, and small fill /
+// copy-back kernels.  All of them are memory-bound copies.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "fdk_internal.h"
+
+namespace fdk {
+namespace {
+
+// ----------------------------------------------------------------- staging
+// One padded row of the staged layout.  Pixel (ip, jp) of the padded image
+// is the detector pixel (ip - 2, jp - 2), zero outside the detector; the quad
+// layout stores the 2x2 block starting at (ip, jp) instead of one pixel.
+template <typename E>
+__device__ __forceinline__ E padded_px(const E* img, const StageArgs& a, int ip, int jp)
+{
+    const int i = ip - kPadLo, j = jp - kPadLo;
+    return (i >= 0 && i < a.W && j >= 0 && j < a.H) ? img[(int64_t)j * a.W + i] : E(0);
+}
+
+__device__ __forceinline__ void stage_row(const StageArgs& a, int64_t local_row)
+{
+    const int k = (int)(local_row / a.Hp);
+    const int jp = (int)(local_row - (int64_t)k * a.Hp);
+    const int j = jp - kPadLo;
+    const bool row_in = j >= 0 && j < a.H;
+    if (a.layout == 1) {
+        if (a.esize == 4) {
+            const float* img = (const float*)a.src + (int64_t)k * a.H * a.W;
+            float4* d = (float4*)(a.dst + (uint64_t)k * a.proj_stride + (uint64_t)jp * a.Wp * 16);
+            for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x)
+                d[ip] = make_float4(padded_px(img, a, ip, jp), padded_px(img, a, ip + 1, jp),
+                                    padded_px(img, a, ip, jp + 1), padded_px(img, a, ip + 1, jp + 1));
+        } else {
+            const unsigned short* img = (const unsigned short*)a.src + (int64_t)k * a.H * a.W;
+            uint2* d = (uint2*)(a.dst + (uint64_t)k * a.proj_stride + (uint64_t)jp * a.Wp * 8);
+            for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x) {
+                const uint32_t t0 = (uint32_t)padded_px(img, a, ip, jp) |
+                                    ((uint32_t)padded_px(img, a, ip + 1, jp) << 16);
+                const uint32_t t1 = (uint32_t)padded_px(img, a, ip, jp + 1) |
+                                    ((uint32_t)padded_px(img, a, ip + 1, jp + 1) << 16);
+                d[ip] = make_uint2(t0, t1);
+            }
+        }
+        return;
+    }
+    if (a.layout == 2) {
+        if (a.esize == 4) {
+            const float* img = (const float*)a.src + (int64_t)k * a.H * a.W;
+            float2* d = (float2*)(a.dst + (uint64_t)k * a.proj_stride + (uint64_t)jp * a.Wp * 8);
+            for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x)
+                d[ip] = make_float2(padded_px(img, a, ip, jp), padded_px(img, a, ip + 1, jp));
+        } else {
+            const unsigned short* img = (const unsigned short*)a.src + (int64_t)k * a.H * a.W;
+            uint32_t* d = (uint32_t*)(a.dst + (uint64_t)k * a.proj_stride + (uint64_t)jp * a.Wp * 4);
+            for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x)
+                d[ip] = (uint32_t)padded_px(img, a, ip, jp) | ((uint32_t)padded_px(img, a, ip + 1, jp) << 16);
+        }
+        return;
+    }
+    unsigned char* drow = a.dst + (uint64_t)k * a.proj_stride + (uint64_t)jp * a.Wp * a.esize;
+    if (a.esize == 4) {
+        const float* src = (const float*)a.src + ((int64_t)k * a.H + (row_in ? j : 0)) * a.W;
+        float* d = (float*)drow;
+        for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x) {
+            const int i = ip - kPadLo;
+            d[ip] = (row_in && i >= 0 && i < a.W) ? src[i] : 0.0f;
+        }
+    } else {
+        const unsigned short* src =
+            (const unsigned short*)a.src + ((int64_t)k * a.H + (row_in ? j : 0)) * a.W;
+        unsigned short* d = (unsigned short*)drow;
+        for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x) {
+            const int i = ip - kPadLo;
+            d[ip] = (row_in && i >= 0 && i < a.W) ? src[i] : (unsigned short)0;
+        }
+    }
+}
+
+// Every workgroup stages kRowsPerBlock consecutive padded rows (one row is
+// only ~1300 pixels, too little work to amortise a workgroup's launch).
+constexpr int kRowsPerBlock = 8;
+
+__global__ __launch_bounds__(256) void stage_kernel(StageArgs a)
+{
+    const int64_t rows = (int64_t)a.n * a.Hp;
+    const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
+    for (int64_t row = r0; row < r0 + kRowsPerBlock && row < rows; ++row) stage_row(a, row);
+}
+
+// Rows of many stacks, numbered stack after stack (StageArgs::row_begin).
+__global__ __launch_bounds__(256) void stage_batched_kernel(const StageArgs* __restrict__ stacks,
+                                                            int n_stacks, int64_t total_rows)
+{
+    const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlock;
+    for (int64_t row = r0; row < r0 + kRowsPerBlock && row < total_rows; ++row) {
+        int lo = 0, hi = n_stacks - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (stacks[mid].row_begin <= row) lo = mid; else hi = mid - 1;
+        }
+        const StageArgs a = stacks[lo];
+        stage_row(a, row - a.row_begin);
+    }
+}
+
+// out[p][0..11] = coef64[p][0..11] / sqrt(scale_p) in FP64 (16 doubles per
+// projection): folding the dequantisation factor into the matrix scales w by
+// 1/sqrt(s), so the kernel's 1/w^2 weight carries s while u/w and v/w are
+// untouched.
+__global__ void fold_kernel(const double* __restrict__ coef64, const float* const* __restrict__ scale_ptrs,
+                            double* __restrict__ out, int n_total)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_total * 16) return;
+    const int p = t >> 4, c = t & 15;
+    if (c >= 12) { out[t] = 0.0; return; }
+    double f = 1.0;
+    if (scale_ptrs != nullptr && scale_ptrs[p] != nullptr) f = 1.0 / sqrt((double)*scale_ptrs[p]);
+    out[t] = coef64[p * 12 + c] * f;
+}
+
+__global__ void fold_single_kernel(const double* __restrict__ coef64, const float* __restrict__ scale,
+                                   double* __restrict__ out, int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * 16) return;
+    const int p = t >> 4, c = t & 15;
+    if (c >= 12) { out[t] = 0.0; return; }
+    const double f = scale != nullptr ? 1.0 / sqrt((double)scale[p]) : 1.0;
+    out[t] = coef64[p * 12 + c] * f;
+}
+
+__global__ void reset_counter_kernel(unsigned* c) { *c = 0u; }
+
+__global__ void fill_kernel(float* __restrict__ p, uint64_t n, float value)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = value;
+}
+
+// out[k][j][i] (+)= padded[k][j + 2][i + 2]
+__global__ __launch_bounds__(256) void unstage_kernel(const float* __restrict__ padded, float* __restrict__ out,
+                                                      int W, int H, int Wp, uint64_t stride_elems,
+                                                      int accumulate)
+{
+    const int64_t row = blockIdx.x;           // k * H + j
+    const int k = (int)(row / H), j = (int)(row - (int64_t)k * H);
+    const float* src = padded + (uint64_t)k * stride_elems + (uint64_t)(j + kPadLo) * Wp + kPadLo;
+    float* dst = out + row * W;
+    for (int i = threadIdx.x; i < W; i += blockDim.x) {
+        const float v = src[i];
+        dst[i] = accumulate ? dst[i] + v : v;
+    }
+}
+
+// ----------------------------------------------------------------- packing
+__global__ __launch_bounds__(256) void absmax_kernel(const float* __restrict__ src, int64_t per_proj,
+                                                     unsigned* __restrict__ maxbits)
+{
+    const int k = blockIdx.y;
+    const float* p = src + (int64_t)k * per_proj;
+    float m = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per_proj;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(p[i]));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    __shared__ float red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        atomicMax(maxbits + k, __float_as_uint(m));   // non-negative floats order like their bits
+    }
+}
+
+__device__ __forceinline__ float pack_scale(unsigned maxbits)
+{
+    const float m = __uint_as_float(maxbits);
+    return m > 0.0f ? m * 0x1p-14f : 1.0f;
+}
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);  // quiet NaN
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ __launch_bounds__(256) void convert_kernel(const float* __restrict__ src, int64_t per_proj,
+                                                      const unsigned* __restrict__ maxbits, int dtype,
+                                                      unsigned short* __restrict__ dst)
+{
+    const int k = blockIdx.y;
+    const float s = pack_scale(maxbits[k]);
+    const float* p = src + (int64_t)k * per_proj;
+    unsigned short* d = dst + (int64_t)k * per_proj;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per_proj;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float q = p[i] / s;
+        d[i] = dtype == 1 ? __half_as_ushort(__float2half_rn(q)) : f32_to_bf16_rne(q);
+    }
+}
+
+__global__ void finalize_scale_kernel(unsigned* __restrict__ maxbits, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) {
+        const float s = pack_scale(maxbits[k]);
+        reinterpret_cast<float*>(maxbits)[k] = s;
+    }
+}
+
+__global__ void zero_u32_kernel(unsigned* p, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0u;
+}
+
+}  // namespace
+
+hipError_t launch_stage(const StageArgs& a, hipStream_t s)
+{
+    const int64_t rows = (int64_t)a.n * a.Hp;
+    hipLaunchKernelGGL(stage_kernel, dim3((unsigned)((rows + kRowsPerBlock - 1) / kRowsPerBlock)), dim3(256), 0,
+                       s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_batched(const StageArgs* dev_args, int n_stacks, int64_t total_rows, hipStream_t s)
+{
+    hipLaunchKernelGGL(stage_batched_kernel,
+                       dim3((unsigned)((total_rows + kRowsPerBlock - 1) / kRowsPerBlock)), dim3(256), 0, s,
+                       dev_args, n_stacks, total_rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(const double* coef64, const float* const* scale_ptrs, double* coef32, int n_total,
+                       hipStream_t s)
+{
+    const int threads = n_total * 16;
+    hipLaunchKernelGGL(fold_kernel, dim3((threads + 255) / 256), dim3(256), 0, s, coef64, scale_ptrs,
+                       coef32, n_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_single(const double* coef64, const float* scale, double* coef32, int n,
+                              hipStream_t s)
+{
+    const int threads = n * 16;
+    hipLaunchKernelGGL(fold_single_kernel, dim3((threads + 255) / 256), dim3(256), 0, s, coef64, scale,
+                       coef32, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(unsigned* counter, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, uint64_t n, float value, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_unstage_add(const float* padded, float* out, int n, int W, int H, int Wp,
+                              uint64_t stride_elems, int accumulate, hipStream_t s)
+{
+    const int64_t rows = (int64_t)n * H;
+    hipLaunchKernelGGL(unstage_kernel, dim3((unsigned)rows), dim3(256), 0, s, padded, out, W, H, Wp,
+                       stride_elems, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* dst, float* scale,
+                       hipStream_t s)
+{
+    const int64_t per = (int64_t)W * H;
+    unsigned* bits = reinterpret_cast<unsigned*>(scale);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, bits, n);
+    int bx = (int)((per + 256 * 16 - 1) / (256 * 16));
+    if (bx < 1) bx = 1;
+    if (bx > 1024) bx = 1024;
+    hipLaunchKernelGGL(absmax_kernel, dim3(bx, n), dim3(256), 0, s, src, per, bits);
+    hipLaunchKernelGGL(convert_kernel, dim3(bx, n), dim3(256), 0, s, src, per, bits, dtype,
+                       (unsigned short*)dst);
+    hipLaunchKernelGGL(finalize_scale_kernel, dim3((n + 255) / 256), dim3(256), 0, s, bits, n);
+    return hipGetLastError();
+}
+
+}  // namespace fdk
