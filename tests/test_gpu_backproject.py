@@ -58,6 +58,25 @@ def test_tilted_carm_general_path(fdk, layout):
     assert_parity(out.cpu().numpy(), ref, what=f"tilted C-arm layout {layout}")
 
 
+@pytest.mark.parametrize("strip,waves", [(16, 4), (2, 1)])
+@pytest.mark.parametrize("tilt", [0.0, 0.4])
+def test_lds_windows_too_large(fdk, strip, waves, tilt):
+    """4 mm voxels on the 0.308 mm-pixel detector: every tile's footprint
+    exceeds the LDS tile, so every projection goes through the gather pass
+    of the LDS kernel (constant-depth and per-voxel variants)."""
+    carm = S.CArm(9, tilt_deg=tilt)
+    mats, q = S.filtered_projections(carm, 12)
+    L, voxel = 40, 4.0
+    fdk.set_tile(fdk.F32, strip, waves, 3)
+    try:
+        out = fdk.backproject(q.to(DEV), fdk.Geometry(mats, carm.width, carm.height), fdk.Volume(L, voxel))
+        torch.cuda.synchronize()
+    finally:
+        fdk.set_tile(fdk.F32, 0, 0)
+    ref = oracle.backproject(L, voxel, mats, q.numpy())
+    assert_parity(out.cpu().numpy(), ref, what=f"oversized windows {strip}x{waves} tilt {tilt}")
+
+
 def test_orbit_plane_geometry_is_constant_w():
     """The default C-arm has w independent of z exactly (the per-strip
     reciprocal path)."""
