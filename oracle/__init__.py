@@ -17,6 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fdk_oracle.c")
+_SRC_FILTER = os.path.join(_HERE, "fdk_filter_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -30,7 +31,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-shared", "-fPIC",
-                        "-std=c11", "-o", tmp, _SRC, "-lm"], check=True)
+                        "-std=gnu11", "-o", tmp, _SRC, _SRC_FILTER, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -54,6 +55,13 @@ def _load():
                                                  _i64, _i64, _dp]
         lib.oracle_supported_updates.restype = _i64
         lib.oracle_num_threads.restype = ctypes.c_int
+        d = ctypes.c_double
+        lib.oracle_parker_weight.argtypes = [d, d, d]
+        lib.oracle_parker_weight.restype = d
+        lib.oracle_ramp_kernel.argtypes = [_i64, d]
+        lib.oracle_ramp_kernel.restype = d
+        lib.oracle_fdk_filter.argtypes = [_i64, _i64, _i64, d, d, d, d, d, d, _dp, d, d, d, _dp, _dp]
+        lib.oracle_fdk_filter.restype = None
         _lib = lib
     return _lib
 
@@ -158,6 +166,33 @@ def supported_updates(L: int, voxel: float, mats, W: int, H: int, origin=None,
     org = _origin(L, voxel, origin)
     return int(lib.oracle_supported_updates(L, float(voxel), _ptr(org), z0, nz, N, W, H,
                                             _ptr(mats)))
+
+
+def parker_weight(beta: float, gamma: float, scan_range: float) -> float:
+    """Short-scan weight of the ray at fan angle gamma in the view at gantry
+    angle beta (Parker 1982); scan_range <= 0 means no weighting."""
+    return float(_load().oracle_parker_weight(float(beta), float(gamma), float(scan_range)))
+
+
+def ramp_kernel(n: int, tau: float) -> float:
+    """Band-limited ramp filter tap h(n) at sample spacing tau (Kak & Slaney)."""
+    return float(_load().oracle_ramp_kernel(int(n), float(tau)))
+
+
+def fdk_filter(proj, pixel_u: float, pixel_v: float, u0: float, v0: float, sdd: float, sid: float,
+               beta, scan_range: float, dbeta: float, fan_sign: float = -1.0) -> np.ndarray:
+    """FDK preprocessing (cosine weight, Parker weight, ramp convolution along
+    rows, scale t * dbeta * SID^2) of line integrals proj (N, H, W), FP64,
+    direct convolution.  See fdk_filter_oracle.c for the formulas."""
+    p = _f64(proj)
+    N, H, W = p.shape
+    b = _f64(beta).ravel()
+    assert b.size == N
+    q = np.empty_like(p)
+    _load().oracle_fdk_filter(N, W, H, float(pixel_u), float(pixel_v), float(u0), float(v0), float(sdd),
+                              float(sid), _ptr(b), float(scan_range), float(dbeta), float(fan_sign),
+                              _ptr(p), _ptr(q))
+    return q
 
 
 def rel_l2(x, ref) -> float:

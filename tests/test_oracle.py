@@ -314,3 +314,101 @@ def test_supported_update_count_matches_paper_workload():
     mats = S.carm_matrices(carm)
     n = oracle.supported_updates(64, 0.5 * 512 / 64, mats, carm.width, carm.height, z_range=(30, 4))
     assert 0 < n <= 64 * 64 * 4 * 8
+
+
+# ----------------------------------------------------------------------------- FDK preprocessing
+def _filter_args(carm):
+    cu, cv = carm.principal_point
+    arc = np.deg2rad(carm.arc_deg)
+    dbeta = arc / (carm.n_proj - 1)
+    return dict(pixel_u=carm.pixel, pixel_v=carm.pixel, u0=cu, v0=cv, sdd=carm.sdd, sid=carm.sid,
+                beta=carm.angles_rad(), scan_range=arc, dbeta=dbeta, fan_sign=-1.0)
+
+
+def test_ramp_kernel_frequency_response():
+    """The band-limited ramp kernel's DTFT is |f| on the band (Kak & Slaney):
+    sum_n h(n) exp(-2 pi i f n) = |f| / tau^2 for |f| <= 1/2 (tau = sample
+    spacing); the truncation of the 1/n^2 tail at |n| < 2^14 costs < 1e-5."""
+    tau = 0.7
+    n = np.arange(-(1 << 14) + 1, 1 << 14)
+    h = np.array([oracle.ramp_kernel(int(k), tau) for k in n])
+    for f in (0.03, 0.1, 0.25, 0.4, 0.49):
+        H = float(np.sum(h * np.cos(2 * np.pi * f * n)))
+        assert H * tau * tau == pytest.approx(f, abs=2e-5)
+    assert oracle.ramp_kernel(0, tau) > 0 and oracle.ramp_kernel(2, tau) == 0.0 and oracle.ramp_kernel(-3, tau) < 0
+
+
+def test_parker_weights_complementary_rays():
+    """Parker's weights give the two measurements of every ray total weight 1:
+    the ray (beta, gamma) is measured again at (beta + pi + 2 gamma, -gamma);
+    outside the short scan the weight is 0 and in its middle 1."""
+    rng = np.random.default_rng(3)
+    R = np.deg2rad(200.0)
+    d = (R - np.pi) / 2
+    for _ in range(2000):
+        g = rng.uniform(-0.9 * d, 0.9 * d)
+        b = rng.uniform(0, np.pi + 2 * d)
+        b2 = b + np.pi + 2 * g
+        if b2 > np.pi + 2 * d:       # the other measurement lies before the scan start
+            b2 = b - np.pi + 2 * g
+            if b2 < 0:
+                continue
+        w = oracle.parker_weight(b, g, R) + oracle.parker_weight(b2, -g, R)
+        assert w == pytest.approx(1.0, abs=1e-12)
+    assert oracle.parker_weight(-0.01, 0.0, R) == 0.0
+    assert oracle.parker_weight(np.pi + 2 * d + 0.01, 0.0, R) == 0.0
+    assert oracle.parker_weight(np.pi / 2, 0.0, R) == 1.0
+    assert oracle.parker_weight(1.0, 0.3, -1.0) == 1.0
+
+
+def test_filter_is_weighted_linear_convolution():
+    """Against numpy's full linear convolution of the weighted rows, with the
+    cosine weight computed as the cosine of the angle between the pixel's ray
+    and the central ray (vector form)."""
+    carm = S.CArm(7, 45, 6, pixel=8.0)
+    a = _filter_args(carm)
+    p = np.random.default_rng(5).standard_normal((7, 6, 45))
+    q = oracle.fdk_filter(p, **a)
+    tau = carm.pixel * carm.sid / carm.sdd
+    W = 45
+    h = np.array([oracle.ramp_kernel(n, tau) for n in range(-(W - 1), W)])
+    u = (np.arange(W) - a["u0"]) * carm.pixel
+    for k in range(7):
+        for j in range(6):
+            v = (j - a["v0"]) * carm.pixel
+            ray = np.stack([u, np.full(W, v), np.full(W, carm.sdd)], axis=1)
+            cosw = ray[:, 2] / np.linalg.norm(ray, axis=1)
+            g = -np.arctan2(u, carm.sdd)
+            wp = np.array([oracle.parker_weight(a["beta"][k], gg, a["scan_range"]) for gg in g])
+            full = np.convolve(p[k, j] * cosw * wp, h)          # length 3W - 2
+            ref = full[W - 1:2 * W - 1] * tau * a["dbeta"] * carm.sid ** 2
+            np.testing.assert_allclose(q[k, j], ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+def test_filter_matches_fft_implementation():
+    """The direct-convolution oracle and the FFT-based host filter of the
+    synthetic input generator (an independent implementation) agree."""
+    carm = S.CArm(9, 64, 12, pixel=6.0)
+    li = np.random.default_rng(6).standard_normal((9, 12, 64))
+    import torch
+    ref = S.fdk_filter(torch.from_numpy(li), carm).numpy()
+    q = oracle.fdk_filter(li, **_filter_args(carm))
+    assert oracle.rel_l2(q, ref) < 1e-12
+
+
+def test_fdk_phantom_sanity_with_oracle_filter():
+    """Oracle filter + oracle backprojection of exact ellipsoid line integrals
+    reproduce the phantom densities near the mid-plane (the scale constants)."""
+    carm = S.CArm(124, 620, 480, pixel=0.616)
+    mats = S.carm_matrices(carm)
+    ph = S.ellipsoid_phantom(0)
+    li = S.project_phantom(mats, carm.width, carm.height, ph).numpy()
+    rows = slice(200, 280)                  # the rows the mid-plane slab projects onto
+    q = np.zeros_like(li)
+    q[:, rows] = oracle.fdk_filter(li[:, rows], **{**_filter_args(carm), "v0": carm.principal_point[1] - 200})
+    L, voxel = 64, 1.5
+    zc = (L // 2 - 4, 8)
+    V = oracle.backproject(L, voxel, mats, q, z_range=zc)
+    T = S.voxelize_phantom(ph, L, voxel).numpy()[L // 2 - 4:L // 2 + 4]
+    assert V.mean() == pytest.approx(T.mean(), rel=0.02)
+    assert oracle.rel_l2(V, T) < 0.10
