@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -96,8 +97,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    ap.add_argument("--legs", default="fp16,bf16,tilted,adjoint,batched,slab1024",
-                    help="comma list of extra legs (fp16,bf16,tilted,adjoint,batched,slab1024) or 'none'")
+    ap.add_argument("--legs", default="fp16,bf16,tilted,adjoint,batched,slab1024,filter",
+                    help="comma list of extra legs (fp16,bf16,tilted,adjoint,batched,slab1024,filter) or 'none'")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only warm-up and timed FP32 steps (for profiler runs)")
     args = ap.parse_args()
@@ -178,6 +179,34 @@ def main() -> int:
         extra[f"{name}_pack_ms"] = pk_ms
         log(f"{name}: {m:.2f} ms/step, {extra[f'{name}_gups']:.1f} GUp/s (pack {pk_ms:.2f} ms, not in step)")
         del qp, sc
+
+    # ---------------------------------------------------------------- FDK preprocessing
+    if "filter" in legs:
+        # line integrals of the same phantom, filtered on the GPU (cosine, Parker, ramp),
+        # against the host generator's FP64 FFT filter
+        li = S.project_phantom(mats, carm.width, carm.height, S.ellipsoid_phantom(0), device=dev).float()
+        q64 = S.fdk_filter(li.double(), carm)    # FP64 filter of the same FP32 input: the kernel's error
+        li = li.contiguous()
+        cu, cv = carm.principal_point
+        arc = math.radians(carm.arc_deg)
+        fg = fdk.FilterGeometry(angles_rad=carm.angles_rad(), width=carm.width, height=carm.height,
+                                pixel_u_mm=carm.pixel, pixel_v_mm=carm.pixel, u0=cu, v0=cv, sdd_mm=carm.sdd,
+                                sid_mm=carm.sid, scan_range_rad=arc, dbeta_rad=arc / (N - 1), fan_sign=-1.0)
+        qf = torch.empty_like(li)
+        m = time_steps(lambda: fdk.filter_projections(li, fg, out=qf), args.steps, args.warmup, stream)
+        mh = time_steps(lambda: fdk.filter_projections(li, fg, dtype=torch.float16), args.steps, args.warmup,
+                        stream)
+        fdk.filter_projections(li, fg, out=qf)
+        torch.cuda.synchronize()
+        err = float(((qf.double() - q64).norm() / q64.norm()).item())
+        nbytes = 2 * li.numel() * 4
+        extra["filter_ms"] = m
+        extra["filter_fp16_ms"] = mh
+        extra["filter_gbps"] = nbytes / (m * 1e-3) / 1e9
+        extra["filter_rel_l2_vs_fp64"] = float(f"{err:.3e}")
+        log(f"filter 496 x 960 x 1248: {m:.2f} ms ({extra['filter_gbps']:.0f} GB/s of 4.75 GB read+write), "
+            f"to FP16 {mh:.2f} ms; rel L2 vs FP64 {err:.2e}")
+        del li, q64, qf
 
     # ---------------------------------------------------------------- general path
     if "tilted" in legs:

@@ -169,6 +169,43 @@ fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width,
                                 int32_t height, int32_t dtype, void* dst,
                                 float* scale_out, void* stream);
 
+/* Geometry of FDK preprocessing (the filtering that turns line integrals
+ * into the projections fdk_backproject consumes). */
+typedef struct fdk_filter_geometry {
+    int32_t n_proj, width, height;  /* N, W (1 .. 2048), H */
+    int32_t reserved;               /* must be 0 */
+    double pixel_u_mm, pixel_v_mm;  /* detector pitch along u (rows) and v (columns) */
+    double u0, v0;                  /* principal point, pixels */
+    double sdd_mm, sid_mm;          /* source-detector and source-isocentre distances */
+    const double* angles_rad;       /* HOST, n_proj gantry angles from the scan start */
+    double scan_range_rad;          /* short-scan range R (Parker weights); <= 0: no weighting */
+    double dbeta_rad;               /* angular step folded into the output scale */
+    double fan_sign;                /* +1 or -1: fan angle = fan_sign * atan(u / SDD) */
+} fdk_filter_geometry;
+
+/*
+ * FDK preprocessing of a stack of line integrals, one projection per image
+ * (Feldkamp-Davis-Kress weighting and filtering; the paper's benchmark data
+ * arrive already filtered, Sec. "RabbitCT Benchmarking Framework"):
+ *   u = (i - u0) pixel_u, v = (j - v0) pixel_v, t = pixel_u SID / SDD
+ *   x_k(i, j) = src_k(i, j) SDD / sqrt(SDD^2 + u^2 + v^2) * parker(beta_k, fan_sign atan(u / SDD))
+ *   dst_k(i, j) = t dbeta SID^2 sum_i' h(i - i') x_k(i', j)
+ * with the band-limited ramp kernel h(0) = 1/(4 t^2), h(odd n) = -1/(n pi t)^2,
+ * h(even n != 0) = 0 (Kak and Slaney) and Parker's short-scan weights for
+ * R = pi + 2 d (Parker 1982); the convolution is the linear one along each
+ * row.  dtype FDK_F32 writes float32 to dst; FDK_F16 / FDK_BF16 write the
+ * packed form of fdk_pack_projections (scale_out required, DEVICE n_proj
+ * floats).  Weights, FFT and convolution run in FP64; only the output is
+ * rounded.
+ *   g          host geometry (angles copied before return)
+ *   src        DEVICE, n_proj * height * width float32
+ *   dst        DEVICE, n_proj * height * width of dtype
+ * FDK_E_GEOMETRY if R > 0 and d = (R - pi) / 2 is smaller than the largest
+ * fan angle of the detector (the short scan does not cover every ray).
+ */
+fdk_status fdk_filter_projections(const fdk_filter_geometry* g, const float* src, void* dst,
+                                  int32_t dtype, float* scale_out, void* stream);
+
 /* Tile shape and staged layout of the backprojection kernel: a 64-wide
  * wavefront owns an 8 x 8 patch of (x, y) columns and each lane a strip of
  * `strip` voxels along z; a workgroup holds `waves` patches (1 x 1, 2 x 1 or
@@ -214,8 +251,9 @@ fdk_status fdk_validate(const fdk_volume* vol, const fdk_projections* proj,
 
 /* Kernel timing for measurement: while enabled, every kernel launch of the
  * library is bracketed by HIP events on its stream.  fdk_profile_read waits for
- * the recorded events and returns, for one kernel kind ("stage", "fold", "bp",
- * "fp", "fill", "unstage", "pack", "batched"), the number of launches and their
+ * the recorded events and returns, for one kernel kind ("stage", "fold",
+ * "window", "bp", "fp", "fill", "unstage", "pack", "batched", "filter"), the
+ * number of launches and their
  * summed duration in milliseconds since the last fdk_profile_enable call
  * (which clears the records). */
 fdk_status fdk_profile_enable(int enable);

@@ -24,7 +24,8 @@ __all__ = [
     "FdkError", "Volume", "Geometry", "F32", "F16", "BF16", "TUNE_ADJOINT", "TUNE_BATCHED", "load", "backproject",
     "forwardproject", "backproject_batched", "pack_projections", "set_tile", "get_tile",
     "load_tuning", "set_tuning_entry", "validate", "release_workspace", "abi_version",
-    "BackProject", "ForwardProject", "Scan", "profile_enable", "profile_read",
+    "BackProject", "ForwardProject", "Scan", "profile_enable", "profile_read", "FilterGeometry",
+    "filter_projections",
 ]
 
 F32, F16, BF16 = 0, 1, 2
@@ -74,6 +75,7 @@ def load():
         "fdk_forwardproject": ([pv, vp, pp, vp, ctypes.c_int, vp], ctypes.c_int),
         "fdk_backproject_batched": ([ps, i32, ctypes.c_int, vp], ctypes.c_int),
         "fdk_pack_projections": ([vp, i32, i32, i32, i32, vp, vp, vp], ctypes.c_int),
+        "fdk_filter_projections": ([ctypes.POINTER(_FilterGeom), vp, vp, i32, vp, vp], ctypes.c_int),
         "fdk_set_tile": ([i32, i32, i32, i32], ctypes.c_int),
         "fdk_get_tile": ([pv, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                          ctypes.c_int),
@@ -269,6 +271,77 @@ def pack_projections(proj: torch.Tensor, dtype=torch.float16, stream=None):
     _check(lib.fdk_pack_projections(_dev_ptr(proj, "projections"), n, w, h, code,
                                     packed.data_ptr(), scale.data_ptr(), _stream(stream)))
     return packed, scale
+
+
+class _FilterGeom(ctypes.Structure):
+    _fields_ = [("n_proj", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("pixel_u_mm", ctypes.c_double), ("pixel_v_mm", ctypes.c_double),
+                ("u0", ctypes.c_double), ("v0", ctypes.c_double), ("sdd_mm", ctypes.c_double),
+                ("sid_mm", ctypes.c_double), ("angles_rad", ctypes.POINTER(ctypes.c_double)),
+                ("scan_range_rad", ctypes.c_double), ("dbeta_rad", ctypes.c_double), ("fan_sign", ctypes.c_double)]
+
+
+@dataclass
+class FilterGeometry:
+    """Geometry of FDK preprocessing (fdk_filter_geometry): detector pitch,
+    principal point (pixels), distances (mm), gantry angles (rad, from the
+    scan start), short-scan range (<= 0: no Parker weights), angular step,
+    orientation of the fan angle."""
+    angles_rad: np.ndarray
+    width: int
+    height: int
+    pixel_u_mm: float
+    pixel_v_mm: float
+    u0: float
+    v0: float
+    sdd_mm: float
+    sid_mm: float
+    scan_range_rad: float
+    dbeta_rad: float
+    fan_sign: float = -1.0
+    _a: np.ndarray = field(init=False, repr=False)
+
+    def __post_init__(self):
+        self._a = np.ascontiguousarray(np.asarray(self.angles_rad, dtype=np.float64).ravel())
+
+    @property
+    def n_proj(self) -> int:
+        return self._a.shape[0]
+
+    def c(self) -> _FilterGeom:
+        g = _FilterGeom()
+        g.n_proj, g.width, g.height, g.reserved = self.n_proj, self.width, self.height, 0
+        g.pixel_u_mm, g.pixel_v_mm, g.u0, g.v0 = self.pixel_u_mm, self.pixel_v_mm, self.u0, self.v0
+        g.sdd_mm, g.sid_mm = self.sdd_mm, self.sid_mm
+        g.angles_rad = self._a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        g.scan_range_rad, g.dbeta_rad, g.fan_sign = self.scan_range_rad, self.dbeta_rad, self.fan_sign
+        return g
+
+
+def filter_projections(lineint: torch.Tensor, fgeom: FilterGeometry, dtype=torch.float32,
+                       out: torch.Tensor = None, stream=None):
+    """FDK preprocessing (cosine and Parker weights, ramp filter along rows)
+    of an (N, H, W) FP32 stack on the device.  Returns the filtered stack,
+    and for dtype float16 / bfloat16 also the per-projection scale of the
+    packed form (None for float32)."""
+    lib = load()
+    if lineint.dim() != 3 or tuple(lineint.shape) != (fgeom.n_proj, fgeom.height, fgeom.width):
+        raise FdkError(-1, f"stack {tuple(lineint.shape)} does not match the filter geometry")
+    if dtype not in _TORCH_DTYPE:
+        raise FdkError(-3, f"output dtype {dtype}")
+    src = _dev_ptr(lineint, "lineint", (torch.float32,))
+    if out is None:
+        out = torch.empty(tuple(lineint.shape), dtype=dtype, device=lineint.device)
+    elif tuple(out.shape) != tuple(lineint.shape):
+        raise FdkError(-1, "output stack has the wrong shape")
+    dst = _dev_ptr(out, "out", (dtype,))
+    scale = None
+    if dtype != torch.float32:
+        scale = torch.empty(fgeom.n_proj, dtype=torch.float32, device=lineint.device)
+    g = fgeom.c()
+    _check(lib.fdk_filter_projections(ctypes.byref(g), src, dst, _TORCH_DTYPE[dtype],
+                                      scale.data_ptr() if scale is not None else None, _stream(stream)))
+    return out, scale
 
 
 def set_tile(dtype: int, strip: int, waves: int, layout: int = 0) -> None:

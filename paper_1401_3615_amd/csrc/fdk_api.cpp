@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -315,6 +316,13 @@ void release_entry(BatchEntry& b)
         release(*x);
 }
 
+// FDK preprocessing tables of one geometry (FP64 on the host, FP32 on the device).
+struct FilterEntry {
+    std::string key;
+    int M = 0;
+    DevBuf hs, tw, wc, wp;
+};
+
 struct DeviceState {
     bool init = false;
     bool arch_ok = false;
@@ -329,6 +337,9 @@ struct DeviceState {
     DevBuf batch_staged;
     std::list<BatchEntry> batch_cache;
     hipStream_t capture_stream = nullptr;
+    // preprocessing
+    std::list<FilterEntry> filter_cache;   // most recent first
+    DevBuf filter_ws;
 };
 
 std::mutex g_mu;
@@ -738,6 +749,198 @@ fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const 
     return end_call(*d, s);
 }
 
+// ------------------------------------------------------------------ FDK preprocessing
+namespace {
+
+constexpr int kMaxFilterWidth = 2048;   // FFT size 4096: 2.25 x 4096 FP64 complex = 144 KiB of LDS
+constexpr size_t kFilterCacheMax = 2;
+
+double ramp_tap(int64_t n, double tau)
+{
+    if (n == 0) return 1.0 / (4.0 * tau * tau);
+    if (n % 2 == 0) return 0.0;
+    const double a = (double)n * M_PI * tau;
+    return -1.0 / (a * a);
+}
+
+double parker(double beta, double gamma, double range)
+{
+    if (range <= 0.0) return 1.0;
+    const double d = 0.5 * (range - M_PI);
+    if (beta < 0.0 || beta > M_PI + 2.0 * d) return 0.0;
+    if (beta < 2.0 * d - 2.0 * gamma) {
+        const double s = std::sin(M_PI / 4.0 * beta / (d - gamma));
+        return s * s;
+    }
+    if (beta <= M_PI - 2.0 * gamma) return 1.0;
+    const double s = std::sin(M_PI / 4.0 * (M_PI + 2.0 * d - beta) / (d + gamma));
+    return s * s;
+}
+
+int filter_size(int W)
+{
+    int M = 4;
+    while (M < 2 * W - 1) M <<= 1;
+    return M;
+}
+
+fdk_status check_filter(const fdk_filter_geometry* g)
+{
+    if (g == nullptr) return fail(FDK_E_INVALID_ARG, "filter geometry is NULL");
+    if (g->reserved != 0) return fail(FDK_E_INVALID_ARG, "reserved field must be 0");
+    if (g->n_proj < 1 || g->height < 1 || g->width < 1 || g->width > kMaxFilterWidth)
+        return fail(FDK_E_INVALID_ARG, "n_proj=%d width=%d height=%d (width 1 .. %d)", g->n_proj, g->width,
+                    g->height, kMaxFilterWidth);
+    if ((int64_t)g->n_proj * g->height * g->width > (int64_t(1) << 40))
+        return fail(FDK_E_INVALID_ARG, "projection stack too large");
+    const double v[] = {g->pixel_u_mm, g->pixel_v_mm, g->u0, g->v0, g->sdd_mm, g->sid_mm, g->scan_range_rad,
+                        g->dbeta_rad};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(FDK_E_INVALID_ARG, "non-finite filter geometry");
+    if (g->pixel_u_mm <= 0.0 || g->pixel_v_mm <= 0.0 || g->sdd_mm <= 0.0 || g->sid_mm <= 0.0)
+        return fail(FDK_E_INVALID_ARG, "pixel pitch and distances must be positive");
+    if (g->fan_sign != 1.0 && g->fan_sign != -1.0) return fail(FDK_E_INVALID_ARG, "fan_sign must be +1 or -1");
+    if (g->angles_rad == nullptr) return fail(FDK_E_INVALID_ARG, "angles_rad is NULL");
+    for (int k = 0; k < g->n_proj; ++k)
+        if (!std::isfinite(g->angles_rad[k])) return fail(FDK_E_INVALID_ARG, "angle %d is not finite", k);
+    if (g->scan_range_rad > 0.0) {
+        double gmax = 0.0;
+        for (int i : {0, g->width - 1})
+            gmax = std::max(gmax, std::fabs(std::atan(((double)i - g->u0) * g->pixel_u_mm / g->sdd_mm)));
+        if (0.5 * (g->scan_range_rad - M_PI) < gmax)
+            return fail(FDK_E_GEOMETRY, "scan range %.4f rad too short for Parker weights (fan half-angle %.4f)",
+                        g->scan_range_rad, gmax);
+    }
+    return FDK_OK;
+}
+
+std::string filter_key(const fdk_filter_geometry* g)
+{
+    std::string key;
+    auto put = [&key](const void* x, size_t n) { key.append(static_cast<const char*>(x), n); };
+    put(g, offsetof(fdk_filter_geometry, angles_rad));
+    put(&g->scan_range_rad, 3 * sizeof(double));
+    put(g->angles_rad, (size_t)g->n_proj * sizeof(double));
+    return key;
+}
+
+// Tables of one geometry: kernel spectrum (gain / M folded in), twiddles,
+// cosine weights (H x W) and short-scan weights (N x W), all from FP64.
+fdk_status filter_tables(DeviceState& d, const fdk_filter_geometry* g, hipStream_t s, FilterEntry** out)
+{
+    std::string key = filter_key(g);
+    for (auto it = d.filter_cache.begin(); it != d.filter_cache.end(); ++it) {
+        if (it->key == key) {
+            d.filter_cache.splice(d.filter_cache.begin(), d.filter_cache, it);
+            *out = &d.filter_cache.front();
+            return FDK_OK;
+        }
+    }
+    const int W = g->width, H = g->height, N = g->n_proj, M = filter_size(W);
+    const double tau = g->pixel_u_mm * g->sid_mm / g->sdd_mm;
+    const double gain = tau * g->dbeta_rad * g->sid_mm * g->sid_mm / (double)M;
+    // spectrum of the circular kernel: h even and zero for |n| >= W, so
+    // H[m] = h(0) + 2 sum_{n = 1 .. W-1} h(n) cos(2 pi m n / M)
+    std::vector<double> cosv(M);
+    for (int t = 0; t < M; ++t) cosv[t] = std::cos(2.0 * M_PI * (double)t / (double)M);
+    std::vector<double> hs(M), wc((size_t)H * W), wp((size_t)N * W);
+    std::vector<double> tw((size_t)M / 2);   // M/4 complex
+    for (int m = 0; m < M; ++m) {
+        double acc = ramp_tap(0, tau);
+        for (int n = 1; n < W; n += 2) acc += 2.0 * ramp_tap(n, tau) * cosv[(int)(((int64_t)m * n) % M)];
+        hs[m] = acc * gain;
+    }
+    for (int t = 0; t < M / 4; ++t) {
+        tw[2 * t] = cosv[t];
+        tw[2 * t + 1] = -std::sin(2.0 * M_PI * (double)t / (double)M);
+    }
+    for (int j = 0; j < H; ++j) {
+        const double v = ((double)j - g->v0) * g->pixel_v_mm;
+        for (int i = 0; i < W; ++i) {
+            const double u = ((double)i - g->u0) * g->pixel_u_mm;
+            wc[(size_t)j * W + i] = g->sdd_mm / std::sqrt(g->sdd_mm * g->sdd_mm + u * u + v * v);
+        }
+    }
+    for (int k = 0; k < N; ++k)
+        for (int i = 0; i < W; ++i) {
+            const double u = ((double)i - g->u0) * g->pixel_u_mm;
+            wp[(size_t)k * W + i] = parker(g->angles_rad[k], g->fan_sign * std::atan(u / g->sdd_mm), g->scan_range_rad);
+        }
+    if (d.filter_cache.size() >= kFilterCacheMax) {
+        HIP_TRY(hipDeviceSynchronize());
+        FilterEntry& b = d.filter_cache.back();
+        release(b.hs); release(b.tw); release(b.wc); release(b.wp);
+        d.filter_cache.pop_back();
+    }
+    FilterEntry f;
+    f.key = std::move(key);
+    f.M = M;
+    const size_t dsz = sizeof(double);
+    hipError_t e = ensure(f.hs, hs.size() * dsz);
+    if (e == hipSuccess) e = ensure(f.tw, tw.size() * dsz);
+    if (e == hipSuccess) e = ensure(f.wc, wc.size() * dsz);
+    if (e == hipSuccess) e = ensure(f.wp, wp.size() * dsz);
+    if (e == hipSuccess) e = hipMemcpyAsync(f.hs.p, hs.data(), hs.size() * dsz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(f.tw.p, tw.data(), tw.size() * dsz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(f.wc.p, wc.data(), wc.size() * dsz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(f.wp.p, wp.data(), wp.size() * dsz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        release(f.hs); release(f.tw); release(f.wc); release(f.wp);
+        return fail(FDK_E_NOMEM, "filter tables: %s", hipGetErrorString(e));
+    }
+    d.filter_cache.push_front(std::move(f));
+    *out = &d.filter_cache.front();
+    return FDK_OK;
+}
+
+}  // namespace
+
+fdk_status fdk_filter_projections(const fdk_filter_geometry* g, const float* src, void* dst, int32_t dtype,
+                                  float* scale_out, void* stream)
+{
+    g_last_error.clear();
+    fdk_status st = check_filter(g);
+    if (st != FDK_OK) return st;
+    if (src == nullptr || dst == nullptr) return fail(FDK_E_INVALID_ARG, "NULL projection pointer");
+    if (dtype != FDK_F32 && dtype != FDK_F16 && dtype != FDK_BF16) return fail(FDK_E_UNSUPPORTED, "dtype %d", dtype);
+    if (dtype != FDK_F32 && scale_out == nullptr) return fail(FDK_E_INVALID_ARG, "scale_out is NULL");
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState* d = nullptr;
+    if ((st = device_state(&d)) != FDK_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = begin_call(*d, s)) != FDK_OK) return st;
+    FilterEntry* f = nullptr;
+    if ((st = filter_tables(*d, g, s, &f)) != FDK_OK) return st;
+    const size_t n_px = (size_t)g->n_proj * g->height * g->width;
+    float* out = static_cast<float*>(dst);
+    if (dtype != FDK_F32) {
+        hipError_t e = ensure(d->filter_ws, n_px * sizeof(float));
+        if (e != hipSuccess) return fail(FDK_E_NOMEM, "filter workspace: %s", hipGetErrorString(e));
+        out = static_cast<float*>(d->filter_ws.p);
+    }
+    FilterArgs a;
+    a.src = src;
+    a.dst = out;
+    a.wc = static_cast<const double*>(f->wc.p);
+    a.wp = static_cast<const double*>(f->wp.p);
+    a.hs = static_cast<const double*>(f->hs.p);
+    a.tw = static_cast<const double2*>(f->tw.p);
+    a.n_proj = g->n_proj;
+    a.W = g->width;
+    a.H = g->height;
+    a.M = f->M;
+    {
+        ProfScope ps("filter", s);
+        HIP_TRY(launch_filter(a, s));
+    }
+    if (dtype != FDK_F32) {
+        ProfScope ps("pack", s);
+        HIP_TRY(launch_pack(out, g->n_proj, g->width, g->height, dtype, dst, scale_out, s));
+    }
+    return end_call(*d, s);
+}
+
 fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width, int32_t height,
                                 int32_t dtype, void* dst, float* scale_out, void* stream)
 {
@@ -1082,6 +1285,11 @@ fdk_status fdk_release_workspace(void)
     }
     d.batch_cache.clear();
     release(d.batch_staged);
+    for (FilterEntry& f : d.filter_cache) {
+        release(f.hs); release(f.tw); release(f.wc); release(f.wp);
+    }
+    d.filter_cache.clear();
+    release(d.filter_ws);
     d.have_last = false;
     return FDK_OK;
 }

@@ -72,6 +72,18 @@ hipError_t launch_fp_band(const BandArgs& b, int group, hipStream_t s);
 int supported_band_group(int group);
 constexpr int kBandCap = 20480;   // FP64 accumulators of one workgroup's detector tiles (160 KiB of LDS)
 
+// FDK preprocessing: weights and ramp filtering of every row (fdk_filter.hip).
+struct FilterArgs {
+    const float* src;            // n_proj x H x W line integrals
+    float* dst;                  // n_proj x H x W filtered (FP32)
+    const double* wc;            // H x W cosine weights
+    const double* wp;            // n_proj x W short-scan weights
+    const double* hs;            // M: real spectrum of the circular ramp kernel x gain / M
+    const double2* tw;           // M / 4 twiddles exp(-2 pi i t / M)
+    int32_t n_proj, W, H, M;     // M: power of two >= 2 W - 1, 2.25 M FP64 complex fit 160 KiB of LDS
+};
+hipError_t launch_filter(const FilterArgs& f, hipStream_t s);
+
 // One projection stack to stage into the padded layout.
 struct StageArgs {
     const void* src;             // [n][H][W] elements of esize bytes

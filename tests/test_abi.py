@@ -228,3 +228,30 @@ def test_autotune_file_round_trip(fdk, tmp_path):
         for strip, waves, layout in autotune.candidates(slot):
             fdk.set_tile(slot, strip, waves, layout)   # every candidate is a compiled shape
         fdk.set_tile(slot, 0, 0)
+
+
+def test_filter_validation(fdk):
+    """Host-side checks of fdk_filter_projections (no device work)."""
+    import numpy as np
+    lib = fdk.load()
+
+    def g(**kw):
+        base = dict(angles_rad=np.linspace(0, 3.49, 4), width=64, height=8, pixel_u_mm=1.0, pixel_v_mm=1.0,
+                    u0=31.5, v0=3.5, sdd_mm=1200.0, sid_mm=750.0, scan_range_rad=3.49, dbeta_rad=0.1,
+                    fan_sign=-1.0)
+        base.update(kw)
+        return fdk.FilterGeometry(**base)
+
+    cases = [(g(width=2049), -1), (g(fan_sign=0.5), -1), (g(sdd_mm=-1.0), -1), (g(pixel_u_mm=float("nan")), -1),
+             (g(scan_range_rad=3.2, pixel_u_mm=10.0), -2), (g(width=0), -1)]
+    for geom, code in cases:
+        c = geom.c()
+        assert lib.fdk_filter_projections(ctypes.byref(c), 1, 1, 0, None, None) == code, lib.fdk_last_error()
+    c = g().c()
+    assert lib.fdk_filter_projections(ctypes.byref(c), None, 1, 0, None, None) == -1
+    assert lib.fdk_filter_projections(ctypes.byref(c), 1, 1, 1, None, None) == -1   # packed needs scale_out
+    assert lib.fdk_filter_projections(ctypes.byref(c), 1, 1, 7, None, None) == -3
+    c.reserved = 1
+    assert lib.fdk_filter_projections(ctypes.byref(c), 1, 1, 0, None, None) == -1
+    assert lib.fdk_filter_projections(None, 1, 1, 0, None, None) == -1
+    assert ctypes.sizeof(fdk._FilterGeom) == 96
