@@ -343,7 +343,9 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    line.update({k: (round(v, 3) if isinstance(v, float) else v) for k, v in extra.items()})
+    # timings and rates to 3 decimals; error figures keep 4 significant digits
+    line.update({k: (float(f"{v:.4g}") if "rel_l2" in k else round(v, 3)) if isinstance(v, float) else v
+                 for k, v in extra.items()})
     print(json.dumps(line), flush=True)
     return 0
 
