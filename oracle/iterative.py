@@ -27,6 +27,9 @@ Least Squares Problems", 1996, Sec. 7.4):
         d      = s + beta d_k
 The k-th iterate minimises ||A x - p|| over x0 + K_k(A^T A, A^T r0).
 
+Landweber (1951), plain gradient descent on 0.5 ||A x - p||^2 with a fixed step:
+    x_{k+1} = x_k + lambda A^T (p - A x_k)
+
 SIRT (simultaneous iterative reconstruction, Gilbert 1972, in the row/column
 normalised form used for cone-beam CT, e.g. Gregor & Benson 2008):
     x_{k+1} = x_k + lambda * C (A^T (R (p - A x_k)))     [then max(., 0) if nonneg]
@@ -125,4 +128,18 @@ def sirt(L: int, voxel: float, mats, proj, n_iter: int, lam: float = 1.0, x0=Non
         x = x + lam * C * At(R * r)
         if nonneg:
             x = np.maximum(x, 0.0)
+    return x, np.array(res2)
+
+
+def landweber(L: int, voxel: float, mats, proj, n_iter: int, lam: float, x0=None, origin=None):
+    """Landweber iteration (FP64).  Returns (x, res2) with res2[k] =
+    ||p - A x_k||^2, k = 0 .. n_iter - 1."""
+    p = _f64(proj)
+    A, At = _ops(L, voxel, mats, p.shape, origin)
+    x = np.zeros((L, L, L)) if x0 is None else _f64(x0).reshape(L, L, L).copy()
+    res2 = []
+    for _ in range(n_iter):
+        r = p - A(x)
+        res2.append(_dot(r, r))
+        x = x + lam * At(r)
     return x, np.array(res2)

@@ -7,6 +7,7 @@ own recursion:
   solved with numpy's lstsq); run to convergence it reaches the minimum-norm
   least-squares solution (lstsq); its recursive residual equals the direct
   one; the residual never grows; degenerate and consistent cases;
+* Landweber: the same closed form with unit weights;
 * SIRT: a closed form through the eigen-decomposition of the symmetrised
   iteration matrix; the row/column weights against the dense matrix's sums;
   a consistent solution is a fixed point; the non-negative variant.
@@ -162,3 +163,23 @@ def test_sirt_fixed_point_and_nonneg():
     np.testing.assert_array_equal(x1n, np.maximum(x1, 0.0))
     x5n, res = IT.sirt(L, 1.0, mats, p, 5, nonneg=True)
     assert np.all(x5n >= 0.0)
+
+
+def test_landweber_spectral_closed_form():
+    """x_k = x_{k-1} + lam A^T (p - A x_{k-1}); with A^T A = V diag(mu) V^T,
+    z = V^T x obeys z_k = (1 - lam mu)^k z_0 + (b / mu)(1 - (1 - lam mu)^k), b = V^T A^T p."""
+    L, W, H, N = 4, 7, 5, 3
+    mats, A, p = _case(L, W, H, N, 14)
+    mu, V = np.linalg.eigh(A.T @ A)
+    lam = 1.5 / mu.max()
+    x0 = np.random.default_rng(15).standard_normal(L ** 3)
+    z0 = V.T @ x0
+    b = V.T @ (A.T @ p.ravel())
+    live = mu > 1e-12 * mu.max()
+    for k in (1, 3, 6):
+        f = (1.0 - lam * mu) ** k
+        zk = np.where(live, f * z0 + np.divide(b, mu, where=live, out=np.zeros_like(b)) * (1.0 - f), z0 + k * lam * b)
+        x, res = IT.landweber(L, 1.0, mats, p, k, lam, x0=x0.reshape(L, L, L))
+        ref = V @ zk
+        assert np.linalg.norm(x.ravel() - ref) <= 1e-10 * np.linalg.norm(ref), k
+        assert res[0] == pytest.approx(float(np.sum((p.ravel() - A @ x0) ** 2)), rel=1e-12)
