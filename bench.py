@@ -97,8 +97,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    ap.add_argument("--legs", default="fp16,bf16,tilted,adjoint,batched,slab1024,filter",
-                    help="comma list of extra legs (fp16,bf16,tilted,adjoint,batched,slab1024,filter) or 'none'")
+    ap.add_argument("--legs", default="fp16,bf16,tilted,adjoint,iterative,batched,slab1024,filter",
+                    help="comma list of extra legs (fp16,bf16,tilted,adjoint,iterative,batched,slab1024,"
+                         "filter) or 'none'")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only warm-up and timed FP32 steps (for profiler runs)")
     args = ap.parse_args()
@@ -231,6 +232,40 @@ def main() -> int:
         extra["adjoint_ms_per_step"] = m
         log(f"adjoint 512^3x496: {m:.2f} ms/step, {extra['adjoint_gups']:.1f} GUp/s")
         del pout
+
+    # ---------------------------------------------------------------- iterative reconstruction
+    if "iterative" in legs:
+        # CGLS and SIRT on the matched pair at 256^3 @ 0.5 mm from the exact line
+        # integrals of the phantom (496 x 1248x960); one iteration = one forward
+        # and one backprojection (2 L^3 N updates) plus the vector kernels
+        Li, voxi = 256, 0.5
+        voli = fdk.Volume(Li, voxi)
+        li = S.project_phantom(mats, carm.width, carm.height, S.ellipsoid_phantom(0), device=dev).float()
+        li = li.contiguous()
+        per_it = 2 * Li ** 3 * N
+        for name, run in (("cgls", lambda n: fdk.cgls(li, geom, voli, n, history=True)),
+                          ("sirt", lambda n: fdk.sirt(li, geom, voli, n, history=True))):
+            n_it = 5
+            run(1)
+            torch.cuda.synchronize()
+            m1 = time_steps(lambda: run(1), 2, 0, stream)
+            fdk.profile_enable(True)
+            m5 = time_steps(lambda: run(n_it), 2, 0, stream)
+            parts = {k: fdk.profile_read(k)[1] / 2 for k in ("fp", "bp", "stage", "window", "fold", "iter")}
+            fdk.profile_enable(False)
+            x, hist = run(n_it)
+            torch.cuda.synchronize()
+            h = hist.cpu().numpy()
+            it_ms = (m5 - m1) / (n_it - 1)
+            extra[f"{name}_ms_per_iter"] = it_ms
+            extra[f"{name}_gups"] = per_it / (it_ms * 1e-3) / 1e9
+            extra[f"{name}_setup_ms"] = m1 - it_ms
+            extra[f"{name}_residual_ratio_5"] = float(h[-1] / h[0])
+            brk = ", ".join(f"{k} {v / n_it:.2f}" for k, v in parts.items())
+            log(f"{name} 256^3 x 496: {it_ms:.2f} ms/iteration ({extra[f'{name}_gups']:.1f} GUp/s over 2 L^3 N), "
+                f"setup {m1 - it_ms:.2f} ms; per-iteration ms by kind: {brk}; ||r_5||^2/||r_0||^2 = {h[-1] / h[0]:.3e}")
+            del x, hist
+        del li
 
     # ---------------------------------------------------------------- 1024^3 in z-slabs
     if "slab1024" in legs:

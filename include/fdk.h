@@ -206,6 +206,48 @@ typedef struct fdk_filter_geometry {
 fdk_status fdk_filter_projections(const fdk_filter_geometry* g, const float* src, void* dst,
                                   int32_t dtype, float* scale_out, void* stream);
 
+/*
+ * Iterative reconstruction on the matched projector pair: the system A x = p
+ * with A = fdk_forwardproject (volume -> projections, the transpose of the
+ * backprojection of Listing 1) and A^T = fdk_backproject.  Each iteration
+ * costs one forward projection, one backprojection and a few passes over
+ * the vectors; step lengths are computed on the device (no host round trip
+ * inside a call).  Vectors are FP32, reductions and scalars FP64.
+ *   vol        grid of the unknown volume (planes z_begin .. z_begin + z_count)
+ *   proj       measured projections p: FP32 only (FDK_E_UNSUPPORTED otherwise),
+ *              DEVICE data, scale ignored
+ *   volume     DEVICE, z_count * L * L float32: the start x0 when requested,
+ *              else overwritten; the result x_n on return
+ *   n_iter     >= 0 iterations
+ *   history    DEVICE doubles or NULL (see each solver)
+ * The library holds four solver vectors (two of the projection stack's size,
+ * two of the volume's) until fdk_release_workspace.  Buffers must not
+ * overlap.  Errors as for the projectors; on a validation error nothing is
+ * enqueued and `volume` is untouched.
+ *
+ * CGLS (conjugate gradients on the normal equations, Hestenes & Stiefel
+ * 1952, in the residual form of Bjorck 1996): x_k minimises ||A x - p|| over
+ * x0 + span{A^T r0, (A^T A) A^T r0, ...} (k vectors), r0 = p - A x0.
+ * history[k] = ||r_k||^2 as carried by the recursion, k = 0 .. n_iter
+ * (n_iter + 1 values).  use_x0: 0 starts from x0 = 0.
+ */
+fdk_status fdk_cgls(const fdk_volume* vol, const fdk_projections* proj, float* volume, int32_t n_iter,
+                    int use_x0, double* history, void* stream);
+
+/*
+ * SIRT (simultaneous iterative reconstruction, Gilbert 1972, with row and
+ * column normalisation):  x <- x + lambda C A^T R (p - A x), then max(x, 0)
+ * with FDK_SIRT_NONNEG.  R and C invert the row sums A 1 and column sums
+ * A^T 1, each floored at 1e-3 times its largest entry: 1 / max(s, 1e-3 max s)
+ * (rows and columns with a zero sum contribute nothing either way).
+ * history[k] = ||p - A x_k||^2 for k = 0 .. n_iter - 1, the residual each
+ * update starts from (n_iter values).  lambda finite and > 0.
+ */
+#define FDK_SIRT_USE_X0 1   /* start from the contents of `volume` (else 0) */
+#define FDK_SIRT_NONNEG 2   /* clamp every iterate at 0 */
+fdk_status fdk_sirt(const fdk_volume* vol, const fdk_projections* proj, float* volume, int32_t n_iter,
+                    double lambda, int32_t flags, double* history, void* stream);
+
 /* Tile shape and staged layout of the backprojection kernel: a 64-wide
  * wavefront owns an 8 x 8 patch of (x, y) columns and each lane a strip of
  * `strip` voxels along z; a workgroup holds `waves` patches (1 x 1, 2 x 1 or

@@ -25,7 +25,7 @@ __all__ = [
     "forwardproject", "backproject_batched", "pack_projections", "set_tile", "get_tile",
     "load_tuning", "set_tuning_entry", "validate", "release_workspace", "abi_version",
     "BackProject", "ForwardProject", "Scan", "profile_enable", "profile_read", "FilterGeometry",
-    "filter_projections",
+    "filter_projections", "cgls", "sirt",
 ]
 
 F32, F16, BF16 = 0, 1, 2
@@ -76,6 +76,8 @@ def load():
         "fdk_backproject_batched": ([ps, i32, ctypes.c_int, vp], ctypes.c_int),
         "fdk_pack_projections": ([vp, i32, i32, i32, i32, vp, vp, vp], ctypes.c_int),
         "fdk_filter_projections": ([ctypes.POINTER(_FilterGeom), vp, vp, i32, vp, vp], ctypes.c_int),
+        "fdk_cgls": ([pv, pp, vp, i32, ctypes.c_int, vp, vp], ctypes.c_int),
+        "fdk_sirt": ([pv, pp, vp, i32, ctypes.c_double, i32, vp, vp], ctypes.c_int),
         "fdk_set_tile": ([i32, i32, i32, i32], ctypes.c_int),
         "fdk_get_tile": ([pv, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                          ctypes.c_int),
@@ -342,6 +344,52 @@ def filter_projections(lineint: torch.Tensor, fgeom: FilterGeometry, dtype=torch
     _check(lib.fdk_filter_projections(ctypes.byref(g), src, dst, _TORCH_DTYPE[dtype],
                                       scale.data_ptr() if scale is not None else None, _stream(stream)))
     return out, scale
+
+
+def _solver_args(proj, geom, vol, x0, name):
+    if proj.dtype != torch.float32:
+        raise FdkError(-3, f"{name} takes float32 projections, got {proj.dtype}")
+    if tuple(proj.shape) != (geom.n_proj, geom.height, geom.width):
+        raise FdkError(-1, f"projections {tuple(proj.shape)} do not match geometry "
+                           f"{(geom.n_proj, geom.height, geom.width)}")
+    shape = (vol.planes, vol.L, vol.L)
+    if x0 is None:
+        out = torch.empty(shape, dtype=torch.float32, device=proj.device)
+    else:
+        if tuple(x0.shape) != shape or x0.dtype != torch.float32:
+            raise FdkError(-1, "start volume has the wrong shape or dtype")
+        out = x0.detach().clone().contiguous()
+    return out
+
+
+def cgls(proj: torch.Tensor, geom: Geometry, vol: Volume, n_iter: int, x0: torch.Tensor = None,
+         history: bool = False, stream=None):
+    """fdk_cgls: n_iter CGLS iterations for min ||A x - p|| with A the
+    forward projector.  Returns the volume, and with history=True also the
+    float64 tensor of ||r_k||^2, k = 0 .. n_iter."""
+    lib = load()
+    out = _solver_args(proj, geom, vol, x0, "cgls")
+    hist = torch.empty(n_iter + 1, dtype=torch.float64, device=proj.device) if history else None
+    v = vol.c()
+    p = geom.c(_dev_ptr(proj, "projections"), F32)
+    _check(lib.fdk_cgls(ctypes.byref(v), ctypes.byref(p), out.data_ptr(), int(n_iter), int(x0 is not None),
+                        hist.data_ptr() if hist is not None else None, _stream(stream)))
+    return (out, hist) if history else out
+
+
+def sirt(proj: torch.Tensor, geom: Geometry, vol: Volume, n_iter: int, lam: float = 1.0,
+         x0: torch.Tensor = None, nonneg: bool = False, history: bool = False, stream=None):
+    """fdk_sirt: n_iter SIRT updates x += lam C A^T R (p - A x).  Returns the
+    volume, and with history=True also ||p - A x_k||^2, k = 0 .. n_iter - 1."""
+    lib = load()
+    out = _solver_args(proj, geom, vol, x0, "sirt")
+    hist = torch.empty(max(n_iter, 1), dtype=torch.float64, device=proj.device) if history else None
+    flags = (1 if x0 is not None else 0) | (2 if nonneg else 0)
+    v = vol.c()
+    p = geom.c(_dev_ptr(proj, "projections"), F32)
+    _check(lib.fdk_sirt(ctypes.byref(v), ctypes.byref(p), out.data_ptr(), int(n_iter), float(lam), flags,
+                        hist.data_ptr() if hist is not None else None, _stream(stream)))
+    return (out, hist[:n_iter]) if history else out
 
 
 def set_tile(dtype: int, strip: int, waves: int, layout: int = 0) -> None:

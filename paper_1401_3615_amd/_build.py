@@ -14,7 +14,7 @@ ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["fdk_kernels.hip", "fdk_stage.hip", "fdk_filter.hip", "fdk_api.cpp"]
+SOURCES = ["fdk_kernels.hip", "fdk_stage.hip", "fdk_filter.hip", "fdk_iter.hip", "fdk_api.cpp"]
 
 
 def hipcc() -> str:

@@ -340,9 +340,13 @@ struct DeviceState {
     // preprocessing
     std::list<FilterEntry> filter_cache;   // most recent first
     DevBuf filter_ws;
+    // iterative solvers: two projection-sized and two volume-sized vectors,
+    // reduction partials and the solver's scalar state
+    DevBuf it_p0, it_p1, it_v0, it_v1, it_part, it_st;
 };
 
-std::mutex g_mu;
+// Recursive: the iterative solvers call the projector entry points while holding it.
+std::recursive_mutex g_mu;
 std::map<int, DeviceState> g_dev;
 Tuning g_tune;
 
@@ -601,7 +605,7 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     fdk_status st = fdk_validate(vol, proj, 1);
     if (st != FDK_OK) return st;
     if (volume == nullptr) return fail(FDK_E_INVALID_ARG, "volume buffer is NULL");
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     load_env_tuning();
     const int es = esize_of(proj->dtype);
     const TileShape t = fit_layout(pick_tile(vol->L, proj->dtype), proj, es);
@@ -705,7 +709,7 @@ fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const 
     if (st != FDK_OK) return st;
     if (volume == nullptr) return fail(FDK_E_INVALID_ARG, "volume buffer is NULL");
     if (proj_out == nullptr) return fail(FDK_E_INVALID_ARG, "projection output is NULL");
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     load_env_tuning();
     const TileShape t = pick_tile(vol->L, kAdjointSlot);
     if (t.layout == 4) return forwardproject_tiles(vol, volume, geom, proj_out, accumulate, stream, t);
@@ -750,6 +754,8 @@ fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const 
 }
 
 // ------------------------------------------------------------------ FDK preprocessing
+}  // extern "C": host helpers below have C++ linkage
+
 namespace {
 
 constexpr int kMaxFilterWidth = 2048;   // FFT size 4096: 2.25 x 4096 FP64 complex = 144 KiB of LDS
@@ -896,6 +902,8 @@ fdk_status filter_tables(DeviceState& d, const fdk_filter_geometry* g, hipStream
 
 }  // namespace
 
+extern "C" {
+
 fdk_status fdk_filter_projections(const fdk_filter_geometry* g, const float* src, void* dst, int32_t dtype,
                                   float* scale_out, void* stream)
 {
@@ -905,7 +913,7 @@ fdk_status fdk_filter_projections(const fdk_filter_geometry* g, const float* src
     if (src == nullptr || dst == nullptr) return fail(FDK_E_INVALID_ARG, "NULL projection pointer");
     if (dtype != FDK_F32 && dtype != FDK_F16 && dtype != FDK_BF16) return fail(FDK_E_UNSUPPORTED, "dtype %d", dtype);
     if (dtype != FDK_F32 && scale_out == nullptr) return fail(FDK_E_INVALID_ARG, "scale_out is NULL");
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     DeviceState* d = nullptr;
     if ((st = device_state(&d)) != FDK_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -941,6 +949,165 @@ fdk_status fdk_filter_projections(const fdk_filter_geometry* g, const float* src
     return end_call(*d, s);
 }
 
+// ------------------------------------------------------------------ iterative solvers
+// CGLS and SIRT for A x = p with A = fdk_forwardproject and A^T =
+// fdk_backproject.  Each iteration is a forward and a backprojection (the
+// projector entry points, called with the library lock held) plus the vector
+// kernels of fdk_iter.hip; step lengths stay in device memory.
+}  // extern "C": host helpers below have C++ linkage
+
+namespace {
+
+// SIRT weights: 1 / max(sum, kSirtFloor * largest sum)
+constexpr double kSirtFloor = 1e-3;
+
+struct IterSetup {
+    DeviceState* d = nullptr;
+    hipStream_t s = nullptr;
+    int64_t nv = 0, np = 0;
+    float *p0 = nullptr, *p1 = nullptr, *v0 = nullptr, *v1 = nullptr;
+    double *part = nullptr, *st = nullptr;
+};
+
+fdk_status iter_setup(const fdk_volume* vol, const fdk_projections* proj, float* volume, int32_t n_iter,
+                      void* stream, IterSetup& it)
+{
+    fdk_status st = fdk_validate(vol, proj, 1);
+    if (st != FDK_OK) return st;
+    if (proj->dtype != FDK_F32) return fail(FDK_E_UNSUPPORTED, "iterative solvers take FP32 projections");
+    if (volume == nullptr) return fail(FDK_E_INVALID_ARG, "volume buffer is NULL");
+    if (n_iter < 0) return fail(FDK_E_INVALID_ARG, "n_iter=%d < 0", n_iter);
+    if ((st = device_state(&it.d)) != FDK_OK) return st;
+    it.s = static_cast<hipStream_t>(stream);
+    it.nv = (int64_t)vol->z_count * vol->L * vol->L;
+    it.np = (int64_t)proj->n_proj * proj->height * proj->width;
+    DeviceState& d = *it.d;
+    const size_t pb = (size_t)it.np * 4, vb = (size_t)it.nv * 4;
+    for (auto [b, bytes] : {std::pair<DevBuf*, size_t>{&d.it_p0, pb}, {&d.it_p1, pb}, {&d.it_v0, vb},
+                            {&d.it_v1, vb}, {&d.it_part, kRedBlocks * sizeof(double)},
+                            {&d.it_st, kStSlots * sizeof(double)}}) {
+        hipError_t e = ensure(*b, bytes);
+        if (e != hipSuccess) return fail(FDK_E_NOMEM, "solver workspace: %s", hipGetErrorString(e));
+    }
+    it.p0 = static_cast<float*>(d.it_p0.p);
+    it.p1 = static_cast<float*>(d.it_p1.p);
+    it.v0 = static_cast<float*>(d.it_v0.p);
+    it.v1 = static_cast<float*>(d.it_v1.p);
+    it.part = static_cast<double*>(d.it_part.p);
+    it.st = static_cast<double*>(d.it_st.p);
+    return begin_call(d, it.s);
+}
+
+// A^T applied to a projection-sized workspace vector.
+fdk_status apply_bp(const fdk_volume* vol, const fdk_projections* proj, const float* src, float* dst,
+                    hipStream_t s)
+{
+    fdk_projections q = *proj;
+    q.data = src;
+    q.dtype = FDK_F32;
+    q.scale = nullptr;
+    return fdk_backproject(vol, &q, dst, 0, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+fdk_status fdk_cgls(const fdk_volume* vol, const fdk_projections* proj, float* volume, int32_t n_iter,
+                    int use_x0, double* history, void* stream)
+{
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
+    load_env_tuning();
+    IterSetup it;
+    fdk_status st = iter_setup(vol, proj, volume, n_iter, stream, it);
+    if (st != FDK_OK) return st;
+    const float* p = static_cast<const float*>(proj->data);
+    float *r = it.p0, *q = it.p1, *sv = it.v0, *dv = it.v1;
+    hipStream_t s = it.s;
+    // r0 = p - A x0 (x0 = 0: r0 = p); the caller's volume is not written
+    // before the first update, so a failing projector call leaves it intact.
+    if (use_x0) {
+        if ((st = fdk_forwardproject(vol, volume, proj, r, 0, s)) != FDK_OK) return st;
+        ProfScope ps("iter", s);
+        HIP_TRY(launch_residual(r, p, nullptr, it.np, it.part, s));
+    } else {
+        HIP_TRY(hipMemcpyAsync(r, p, it.np * 4, hipMemcpyDeviceToDevice, s));
+        ProfScope ps("iter", s);
+        HIP_TRY(launch_sumsq(r, it.np, it.part, s));
+    }
+    HIP_TRY(launch_scalar(it.part, it.st, history, kOpHist, 0, s));
+    if ((st = apply_bp(vol, proj, r, sv, s)) != FDK_OK) return st;      // s0 = A^T r0
+    {
+        ProfScope ps("iter", s);
+        HIP_TRY(launch_sumsq(sv, it.nv, it.part, s));
+        HIP_TRY(launch_scalar(it.part, it.st, nullptr, kOpStore, kStGamma, s));
+        HIP_TRY(hipMemcpyAsync(dv, sv, it.nv * 4, hipMemcpyDeviceToDevice, s));   // d0 = s0
+        if (!use_x0) HIP_TRY(launch_fill(volume, (uint64_t)it.nv, 0.0f, s));
+    }
+    for (int k = 1; k <= n_iter; ++k) {
+        if ((st = fdk_forwardproject(vol, dv, proj, q, 0, s)) != FDK_OK) return st;   // q = A d
+        {
+            ProfScope ps("iter", s);
+            HIP_TRY(launch_sumsq(q, it.np, it.part, s));
+            HIP_TRY(launch_scalar(it.part, it.st, nullptr, kOpAlpha, 0, s));
+            HIP_TRY(launch_cgls_update(volume, dv, it.nv, r, q, it.np, it.st, it.part, s));
+            HIP_TRY(launch_scalar(it.part, it.st, history, kOpHist, k, s));
+        }
+        if ((st = apply_bp(vol, proj, r, sv, s)) != FDK_OK) return st;  // s = A^T r
+        ProfScope ps("iter", s);
+        HIP_TRY(launch_sumsq(sv, it.nv, it.part, s));
+        HIP_TRY(launch_scalar(it.part, it.st, nullptr, kOpBeta, 0, s));
+        HIP_TRY(launch_cgls_direction(dv, sv, it.nv, it.st, s));
+    }
+    return end_call(*it.d, s);
+}
+
+fdk_status fdk_sirt(const fdk_volume* vol, const fdk_projections* proj, float* volume, int32_t n_iter,
+                    double lambda, int32_t flags, double* history, void* stream)
+{
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
+    load_env_tuning();
+    if (!std::isfinite(lambda) || !(lambda > 0.0))
+        return fail(FDK_E_INVALID_ARG, "lambda must be finite and > 0");
+    if (flags & ~(FDK_SIRT_USE_X0 | FDK_SIRT_NONNEG)) return fail(FDK_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    IterSetup it;
+    fdk_status st = iter_setup(vol, proj, volume, n_iter, stream, it);
+    if (st != FDK_OK) return st;
+    const float* p = static_cast<const float*>(proj->data);
+    float *r = it.p0, *rw = it.p1, *t = it.v0, *cw = it.v1;
+    hipStream_t s = it.s;
+    // row sums A 1 -> rw, column sums A^T 1 -> cw, each inverted with the floor
+    {
+        ProfScope ps("iter", s);
+        HIP_TRY(launch_fill(t, (uint64_t)it.nv, 1.0f, s));
+        HIP_TRY(launch_fill(r, (uint64_t)it.np, 1.0f, s));
+    }
+    if ((st = fdk_forwardproject(vol, t, proj, rw, 0, s)) != FDK_OK) return st;
+    if ((st = apply_bp(vol, proj, r, cw, s)) != FDK_OK) return st;
+    {
+        ProfScope ps("iter", s);
+        HIP_TRY(launch_max(rw, it.np, it.part, s));
+        HIP_TRY(launch_scalar(it.part, it.st, nullptr, kOpMax, kStRowMax, s));
+        HIP_TRY(launch_inv_floor(rw, it.np, it.st, kStRowMax, kSirtFloor, s));
+        HIP_TRY(launch_max(cw, it.nv, it.part, s));
+        HIP_TRY(launch_scalar(it.part, it.st, nullptr, kOpMax, kStColMax, s));
+        HIP_TRY(launch_inv_floor(cw, it.nv, it.st, kStColMax, kSirtFloor, s));
+        if (!(flags & FDK_SIRT_USE_X0)) HIP_TRY(launch_fill(volume, (uint64_t)it.nv, 0.0f, s));
+    }
+    for (int k = 0; k < n_iter; ++k) {
+        if ((st = fdk_forwardproject(vol, volume, proj, r, 0, s)) != FDK_OK) return st;   // A x
+        {
+            ProfScope ps("iter", s);
+            HIP_TRY(launch_residual(r, p, rw, it.np, it.part, s));   // R (p - A x)
+            HIP_TRY(launch_scalar(it.part, it.st, history, kOpHist, k, s));
+        }
+        if ((st = apply_bp(vol, proj, r, t, s)) != FDK_OK) return st;
+        ProfScope ps("iter", s);
+        HIP_TRY(launch_sirt_update(volume, t, cw, it.nv, lambda, (flags & FDK_SIRT_NONNEG) ? 1 : 0, s));
+    }
+    return end_call(*it.d, s);
+}
+
 fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width, int32_t height,
                                 int32_t dtype, void* dst, float* scale_out, void* stream)
 {
@@ -950,7 +1117,7 @@ fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width,
     if (n_proj < 1 || width < 1 || height < 1) return fail(FDK_E_INVALID_ARG, "empty projection stack");
     if (n_proj > 65535) return fail(FDK_E_INVALID_ARG, "n_proj=%d > 65535", n_proj);
     if (dtype != FDK_F16 && dtype != FDK_BF16) return fail(FDK_E_UNSUPPORTED, "pack dtype must be F16 or BF16");
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     DeviceState* d = nullptr;
     fdk_status st = device_state(&d);
     if (st != FDK_OK) return st;
@@ -976,7 +1143,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         if (scans[i].volume == nullptr) return fail(FDK_E_INVALID_ARG, "scan %d: volume buffer is NULL", i);
         maxL = std::max(maxL, scans[i].vol.L);
     }
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     load_env_tuning();
     // one tile shape (strip, waves) for the whole batch, from the batched slot;
     // FP32 scans take its layout, FP16/BF16 scans the layout of their own slot
@@ -1175,7 +1342,7 @@ fdk_status fdk_set_tile(int32_t dtype, int32_t strip, int32_t waves, int32_t lay
 {
     g_last_error.clear();
     if (dtype < 0 || dtype >= kSlots) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     if (strip == 0 && waves == 0) {
         g_tune.forced[dtype] = {0, 0, 0};
         return FDK_OK;
@@ -1195,7 +1362,7 @@ fdk_status fdk_get_tile(const fdk_volume* vol, int32_t dtype, int32_t* strip, in
     if (st != FDK_OK) return st;
     if (dtype < 0 || dtype >= kSlots) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
     if (strip == nullptr || waves == nullptr || layout == nullptr) return fail(FDK_E_INVALID_ARG, "NULL output");
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     load_env_tuning();
     const TileShape t = pick_tile(vol->L, dtype);
     *strip = t.strip;
@@ -1210,7 +1377,7 @@ fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip
     g_last_error.clear();
     if (dtype < 0 || dtype >= kSlots) return fail(FDK_E_UNSUPPORTED, "unknown tuning slot %d", dtype);
     if (size_class < 0 || size_class > 15) return fail(FDK_E_INVALID_ARG, "size class %d", size_class);
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     if (strip == 0 && waves == 0) {
         g_tune.table.erase({dtype, size_class});
         return FDK_OK;
@@ -1259,7 +1426,7 @@ int32_t fdk_load_tuning(const char* path)
     }
     std::fclose(f);
     if (!header) return fail(FDK_E_INVALID_ARG, "%s: missing 'fdk-tuning' header", path);
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     for (auto& e : entries) g_tune.table[e.first] = e.second;
     return n;
 }
@@ -1267,7 +1434,7 @@ int32_t fdk_load_tuning(const char* path)
 fdk_status fdk_release_workspace(void)
 {
     g_last_error.clear();
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     auto it = g_dev.find(dev);
@@ -1290,6 +1457,7 @@ fdk_status fdk_release_workspace(void)
     }
     d.filter_cache.clear();
     release(d.filter_ws);
+    for (DevBuf* b : {&d.it_p0, &d.it_p1, &d.it_v0, &d.it_v1, &d.it_part, &d.it_st}) release(*b);
     d.have_last = false;
     return FDK_OK;
 }
@@ -1297,7 +1465,7 @@ fdk_status fdk_release_workspace(void)
 fdk_status fdk_profile_enable(int enable)
 {
     g_last_error.clear();
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     for (ProfRecord& r : g_prof.records) {
         (void)hipEventSynchronize(r.end);
         g_prof.pool.push_back(r.start);
@@ -1313,7 +1481,7 @@ fdk_status fdk_profile_read(const char* kernel, int64_t* launches, double* total
     g_last_error.clear();
     if (kernel == nullptr || launches == nullptr || total_ms == nullptr)
         return fail(FDK_E_INVALID_ARG, "NULL argument");
-    std::lock_guard<std::mutex> lock(g_mu);
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
     int64_t n = 0;
     double ms = 0.0;
     for (ProfRecord& r : g_prof.records) {

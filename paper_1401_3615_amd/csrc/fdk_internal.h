@@ -84,6 +84,23 @@ struct FilterArgs {
 };
 hipError_t launch_filter(const FilterArgs& f, hipStream_t s);
 
+// Iterative solvers (fdk_iter.hip).  Reductions write one FP64 partial per
+// workgroup of a fixed grid of kRedBlocks; scalar_kernel combines them and
+// applies an op to the solver state `st` (slots kSt*).
+constexpr int kRedBlocks = 1024;
+enum { kStGamma = 0, kStAlpha = 1, kStBeta = 2, kStQQ = 3, kStRowMax = 4, kStColMax = 5, kStSlots = 8 };
+enum { kOpStore = 0, kOpAlpha = 1, kOpBeta = 2, kOpHist = 3, kOpMax = 4 };
+hipError_t launch_sumsq(const float* a, int64_t n, double* part, hipStream_t s);
+hipError_t launch_max(const float* a, int64_t n, double* part, hipStream_t s);
+hipError_t launch_scalar(const double* part, double* st, double* hist, int op, int slot, hipStream_t s);
+hipError_t launch_cgls_update(float* x, const float* d, int64_t nv, float* r, const float* q, int64_t np,
+                              const double* st, double* part, hipStream_t s);
+hipError_t launch_cgls_direction(float* d, const float* sv, int64_t n, const double* st, hipStream_t s);
+hipError_t launch_residual(float* r, const float* p, const float* w, int64_t n, double* part, hipStream_t s);
+hipError_t launch_sirt_update(float* x, const float* t, const float* c, int64_t n, double lambda, int nonneg,
+                              hipStream_t s);
+hipError_t launch_inv_floor(float* a, int64_t n, const double* st, int slot, double floor_rel, hipStream_t s);
+
 // One projection stack to stage into the padded layout.
 struct StageArgs {
     const void* src;             // [n][H][W] elements of esize bytes

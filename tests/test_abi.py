@@ -255,3 +255,27 @@ def test_filter_validation(fdk):
     assert lib.fdk_filter_projections(ctypes.byref(c), 1, 1, 0, None, None) == -1
     assert lib.fdk_filter_projections(None, 1, 1, 0, None, None) == -1
     assert ctypes.sizeof(fdk._FilterGeom) == 96
+
+
+def test_solver_validation(fdk):
+    """Host-side checks of fdk_cgls / fdk_sirt (no device work)."""
+    lib = fdk.load()
+    mats, W, H = _case()
+    v = fdk.Volume(16, 1.0).c()
+    p = fdk.Geometry(mats, W, H).c(1, fdk.F32)
+    assert lib.fdk_cgls(ctypes.byref(v), ctypes.byref(p), None, 2, 0, None, None) == -1   # no volume
+    assert lib.fdk_cgls(ctypes.byref(v), ctypes.byref(p), 1, -1, 0, None, None) == -1     # n_iter < 0
+    assert lib.fdk_sirt(ctypes.byref(v), ctypes.byref(p), 1, 2, 0.0, 0, None, None) == -1  # lambda
+    assert lib.fdk_sirt(ctypes.byref(v), ctypes.byref(p), 1, 2, float("nan"), 0, None, None) == -1
+    assert lib.fdk_sirt(ctypes.byref(v), ctypes.byref(p), 1, 2, 1.0, 4, None, None) == -1  # flags
+    p16 = fdk.Geometry(mats, W, H).c(1, fdk.F16)
+    assert lib.fdk_cgls(ctypes.byref(v), ctypes.byref(p16), 1, 2, 0, None, None) == -3
+    assert lib.fdk_sirt(ctypes.byref(v), ctypes.byref(p16), 1, 2, 1.0, 0, None, None) == -3
+    p0 = fdk.Geometry(mats, W, H).c(None, fdk.F32)
+    assert lib.fdk_cgls(ctypes.byref(v), ctypes.byref(p0), 1, 2, 0, None, None) == -1     # no data
+    behind = mats.copy()
+    behind[1] *= -1.0
+    pb = fdk.Geometry(behind, W, H).c(1, fdk.F32)
+    assert lib.fdk_cgls(ctypes.byref(v), ctypes.byref(pb), 1, 2, 0, None, None) == -2
+    assert lib.fdk_sirt(ctypes.byref(v), ctypes.byref(pb), 1, 2, 1.0, 0, None, None) == -2
+    assert b"projection 1" in lib.fdk_last_error()
