@@ -97,9 +97,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    ap.add_argument("--legs", default="fp16,bf16,tilted,adjoint,iterative,batched,slab1024,filter",
+    ap.add_argument("--legs", default="fp16,bf16,tilted,adjoint,iterative,batched,slab1024,streamed,filter",
                     help="comma list of extra legs (fp16,bf16,tilted,adjoint,iterative,batched,slab1024,"
-                         "filter) or 'none'")
+                         "streamed,filter) or 'none'")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only warm-up and timed FP32 steps (for profiler runs)")
     args = ap.parse_args()
@@ -282,6 +282,31 @@ def main() -> int:
         extra["slab1024_ms_per_step"] = m
         log(f"1024^3 x 496 in {len(slabs)} z-slabs: {m:.1f} ms, {extra['slab1024_gups']:.1f} GUp/s")
         del big
+
+    # ---------------------------------------------------------------- out-of-core
+    if "streamed" in legs:
+        # the 1024^3 volume with the projection stack in pinned host memory: each
+        # 128-plane slab receives only its detector row band over PCIe while the
+        # previous slab is backprojected; then the volume kept in host memory too
+        L2, vox2, slab = 1024, 0.25, 128
+        base = fdk.Volume(L2, vox2)
+        host_q = q.cpu().pin_memory()
+        rows, _ = fdk.streamed_plan(geom, base, slab)
+        h2d = float(rows.sum()) * N * carm.width * 4
+        big = torch.empty((L2, L2, L2), dtype=torch.float32, device=dev)
+        m = time_steps(lambda: fdk.backproject_streamed(host_q, geom, base, slab, out=big), 2, 1, stream)
+        extra["streamed1024_gups"] = L2 ** 3 * N / (m * 1e-3) / 1e9
+        extra["streamed1024_ms_per_step"] = m
+        extra["streamed1024_h2d_gb"] = h2d / 1e9
+        del big
+        hv = torch.empty((L2, L2, L2), dtype=torch.float32).pin_memory()
+        mh = time_steps(lambda: fdk.backproject_streamed(host_q, geom, base, slab, out=hv), 2, 1, stream)
+        extra["streamed1024_host_volume_gups"] = L2 ** 3 * N / (mh * 1e-3) / 1e9
+        extra["streamed1024_host_volume_ms_per_step"] = mh
+        log(f"1024^3 x 496 streamed from host ({h2d / 1e9:.2f} GB of row bands over PCIe per pass): {m:.1f} ms, "
+            f"{extra['streamed1024_gups']:.1f} GUp/s; volume in host memory too: {mh:.1f} ms, "
+            f"{extra['streamed1024_host_volume_gups']:.1f} GUp/s")
+        del hv, host_q
 
     # ---------------------------------------------------------------- batched
     if "batched" in legs:

@@ -207,6 +207,47 @@ fdk_status fdk_filter_projections(const fdk_filter_geometry* g, const float* src
                                   int32_t dtype, float* scale_out, void* stream);
 
 /*
+ * Out-of-core backprojection, for stacks and volumes that should not (or
+ * cannot) be resident on the device: the paper's outlook to very large
+ * detectors (Sec. "Conclusion and Outlook").  The volume is processed in
+ * z-slabs of `slab_planes` planes; for each slab and projection only the
+ * band of detector rows the slab can reach is copied to the device (from
+ * the slab's corner voxels, exact for w > 0, widened by two rows), on a
+ * library copy stream, while the previous slab is backprojected on
+ * `stream`.  The band's first row is folded into the matrix in FP64
+ * (v' = v - j0 w), so each slab is an ordinary fdk_backproject call on a
+ * band-high detector; results equal fdk_backproject on the whole stack up
+ * to FP32 rounding.
+ *   vol          grid (planes z_begin .. z_begin + z_count)
+ *   proj         n_proj, width, height, mats, dtype, scale as for
+ *                fdk_backproject; data may be HOST or DEVICE memory (page-locked
+ *                host memory lets the copies overlap the kernels; pageable
+ *                memory is copied synchronously by the runtime)
+ *   volume       DEVICE z_count * L * L float32, or HOST memory with
+ *                FDK_STREAM_HOST_VOLUME (each slab is computed into one of two
+ *                device slab buffers and copied back on a second copy stream;
+ *                with accumulate the slab is first copied in)
+ *   slab_planes  >= 1 planes per slab (the last slab may be thinner)
+ * Device memory held until fdk_release_workspace: two band stacks of
+ * n_proj * (largest band) * width elements, and with FDK_STREAM_HOST_VOLUME
+ * two slabs of slab_planes * L * L float32.  The call returns once all work
+ * is enqueued; `stream` completes when the volume (host or device) is
+ * written.  The host buffers must stay valid until then.  Errors as for
+ * fdk_backproject; every slab is validated before anything is enqueued.
+ */
+#define FDK_STREAM_HOST_VOLUME 1
+fdk_status fdk_backproject_streamed(const fdk_volume* vol, const fdk_projections* proj, float* volume,
+                                    int32_t slab_planes, int32_t flags, int accumulate, void* stream);
+
+/* The slab plan fdk_backproject_streamed would use (host only, no device
+ * work): *n_slabs slabs; band_rows[s] (HOST, n_slabs entries, or NULL) rows
+ * copied per projection for slab s; first_rows[s * n_proj + k] (HOST, or NULL)
+ * the first detector row of projection k's band.  Call with NULL arrays to
+ * get n_slabs = ceil(z_count / slab_planes). */
+fdk_status fdk_streamed_plan(const fdk_volume* vol, const fdk_projections* proj, int32_t slab_planes,
+                             int32_t* n_slabs, int32_t* band_rows, int32_t* first_rows);
+
+/*
  * Iterative reconstruction on the matched projector pair: the system A x = p
  * with A = fdk_forwardproject (volume -> projections, the transpose of the
  * backprojection of Listing 1) and A^T = fdk_backproject.  Each iteration

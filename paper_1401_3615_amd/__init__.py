@@ -25,7 +25,7 @@ __all__ = [
     "forwardproject", "backproject_batched", "pack_projections", "set_tile", "get_tile",
     "load_tuning", "set_tuning_entry", "validate", "release_workspace", "abi_version",
     "BackProject", "ForwardProject", "Scan", "profile_enable", "profile_read", "FilterGeometry",
-    "filter_projections", "cgls", "sirt",
+    "filter_projections", "cgls", "sirt", "backproject_streamed", "streamed_plan",
 ]
 
 F32, F16, BF16 = 0, 1, 2
@@ -77,6 +77,8 @@ def load():
         "fdk_pack_projections": ([vp, i32, i32, i32, i32, vp, vp, vp], ctypes.c_int),
         "fdk_filter_projections": ([ctypes.POINTER(_FilterGeom), vp, vp, i32, vp, vp], ctypes.c_int),
         "fdk_cgls": ([pv, pp, vp, i32, ctypes.c_int, vp, vp], ctypes.c_int),
+        "fdk_backproject_streamed": ([pv, pp, vp, i32, i32, ctypes.c_int, vp], ctypes.c_int),
+        "fdk_streamed_plan": ([pv, pp, i32, ctypes.POINTER(i32), vp, vp], ctypes.c_int),
         "fdk_sirt": ([pv, pp, vp, i32, ctypes.c_double, i32, vp, vp], ctypes.c_int),
         "fdk_set_tile": ([i32, i32, i32, i32], ctypes.c_int),
         "fdk_get_tile": ([pv, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
@@ -230,6 +232,49 @@ def forwardproject(volume: torch.Tensor, geom: Geometry, vol: Volume, out: torch
                                   ctypes.byref(p), _dev_ptr(out, "projections", (torch.float32,)),
                                   int(bool(accumulate)), _stream(stream)))
     return out
+
+
+def backproject_streamed(proj: torch.Tensor, geom: Geometry, vol: Volume, slab_planes: int,
+                         out: torch.Tensor = None, accumulate: bool = False, scale: torch.Tensor = None,
+                         stream=None) -> torch.Tensor:
+    """fdk_backproject_streamed: the projection stack may live in host memory
+    (pin it for overlap); each z-slab of `slab_planes` planes receives only
+    its detector row band.  `out` on the CPU keeps the volume in host memory
+    (FDK_STREAM_HOST_VOLUME); default: a new device volume.  The CPU tensors
+    must stay alive until the stream has completed."""
+    lib = load()
+    if proj.dtype not in _TORCH_DTYPE:
+        raise FdkError(-3, f"projection dtype {proj.dtype}")
+    if tuple(proj.shape) != (geom.n_proj, geom.height, geom.width) or not proj.is_contiguous():
+        raise FdkError(-1, "projections must be a contiguous (N, H, W) stack matching the geometry")
+    if out is None:
+        out = torch.empty((vol.planes, vol.L, vol.L), dtype=torch.float32, device="cuda")
+    if tuple(out.shape) != (vol.planes, vol.L, vol.L) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise FdkError(-1, "output volume has the wrong shape, dtype or layout")
+    sp = None
+    if scale is not None:
+        if scale.numel() != geom.n_proj:
+            raise FdkError(-1, "scale must have one entry per projection")
+        sp = _dev_ptr(scale, "scale", (torch.float32,))
+    v = vol.c()
+    p = geom.c(proj.data_ptr(), _TORCH_DTYPE[proj.dtype], sp)
+    flags = 0 if out.is_cuda else 1
+    _check(lib.fdk_backproject_streamed(ctypes.byref(v), ctypes.byref(p), out.data_ptr(), int(slab_planes), flags,
+                                        int(bool(accumulate)), _stream(stream)))
+    return out
+
+
+def streamed_plan(geom: Geometry, vol: Volume, slab_planes: int):
+    """(band_rows (S,), first_rows (S, N)) of fdk_backproject_streamed's slab plan."""
+    lib = load()
+    v, p = vol.c(), geom.c()
+    n = ctypes.c_int32()
+    _check(lib.fdk_streamed_plan(ctypes.byref(v), ctypes.byref(p), int(slab_planes), ctypes.byref(n), None, None))
+    rows = np.zeros(n.value, dtype=np.int32)
+    first = np.zeros((n.value, geom.n_proj), dtype=np.int32)
+    _check(lib.fdk_streamed_plan(ctypes.byref(v), ctypes.byref(p), int(slab_planes), ctypes.byref(n),
+                                 rows.ctypes.data, first.ctypes.data))
+    return rows, first
 
 
 @dataclass

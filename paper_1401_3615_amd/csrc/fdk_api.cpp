@@ -343,6 +343,13 @@ struct DeviceState {
     // iterative solvers: two projection-sized and two volume-sized vectors,
     // reduction partials and the solver's scalar state
     DevBuf it_p0, it_p1, it_v0, it_v1, it_part, it_st;
+    // out-of-core form: double-buffered row-band stacks and volume slabs,
+    // a host-to-device and a device-to-host copy stream, and the events that
+    // order the buffers between the streams (kept across calls)
+    DevBuf band[2], slab[2];
+    hipStream_t h2d = nullptr, d2h = nullptr;
+    hipEvent_t band_ready[2] = {}, band_free[2] = {}, slab_done[2] = {}, slab_free[2] = {};
+    bool band_used[2] = {false, false}, slab_used[2] = {false, false};
 };
 
 // Recursive: the iterative solvers call the projector entry points while holding it.
@@ -1108,6 +1115,207 @@ fdk_status fdk_sirt(const fdk_volume* vol, const fdk_projections* proj, float* v
     return end_call(*it.d, s);
 }
 
+// ------------------------------------------------------------------ out-of-core form
+}  // extern "C": host helpers below have C++ linkage
+
+namespace {
+
+// Rows of the detector that the voxel centres of planes [z0, z0 + nz) can
+// reach in projection k, widened by two rows on each side for the FP32
+// rounding of the kernel's coordinates.  v/w is linear-fractional with w > 0
+// over the box, so its extremes lie at the box's corners.  Returns false if
+// the box projects entirely above or below the detector (then *below says
+// which side).
+bool band_rows(const fdk_volume* v, const double* A, int H, int z0, int nz, int* lo, int* hi, bool* below)
+{
+    double mn = 1e300, mx = -1e300;
+    for (int c = 0; c < 8; ++c) {
+        const double X = v->origin_mm[0] + ((c & 1) ? v->L - 1 : 0) * v->voxel_mm;
+        const double Y = v->origin_mm[1] + ((c & 2) ? v->L - 1 : 0) * v->voxel_mm;
+        const double Z = v->origin_mm[2] + ((c & 4) ? z0 + nz - 1 : z0) * v->voxel_mm;
+        const double iy = (A[4] * X + A[5] * Y + A[6] * Z + A[7]) / (A[8] * X + A[9] * Y + A[10] * Z + A[11]);
+        mn = std::min(mn, iy);
+        mx = std::max(mx, iy);
+    }
+    const double l = std::floor(mn) - 2.0, h = std::floor(mx) + 3.0;
+    *below = l > (double)(H - 1);
+    if (h < 0.0 || l > (double)(H - 1)) return false;
+    *lo = (int)std::max(l, 0.0);
+    *hi = (int)std::min(h, (double)(H - 1));
+    return true;
+}
+
+struct SlabPlan {
+    int z0, nz, rows;
+    std::vector<int> j0;         // first detector row of each projection's band
+    std::vector<double> mats;    // matrices with the row offset folded in: v' = v - j0 w
+};
+
+std::vector<SlabPlan> plan_slabs(const fdk_volume* v, const fdk_projections* p, int slab_planes)
+{
+    std::vector<SlabPlan> plan;
+    const int N = p->n_proj, H = p->height;
+    for (int z0 = v->z_begin; z0 < v->z_begin + v->z_count; z0 += slab_planes) {
+        SlabPlan sp;
+        sp.z0 = z0;
+        sp.nz = std::min(slab_planes, v->z_begin + v->z_count - z0);
+        std::vector<int> lo(N), hi(N);
+        std::vector<char> hit(N), below(N);
+        sp.rows = 1;
+        for (int k = 0; k < N; ++k) {
+            bool b = false;
+            hit[k] = band_rows(v, p->mats + 12 * k, H, sp.z0, sp.nz, &lo[k], &hi[k], &b);
+            below[k] = b;
+            if (hit[k]) sp.rows = std::max(sp.rows, hi[k] - lo[k] + 1);
+        }
+        sp.j0.resize(N);
+        sp.mats.assign(p->mats, p->mats + 12 * (size_t)N);
+        for (int k = 0; k < N; ++k) {
+            // a band that misses the detector is placed on the side the box lies on,
+            // so every tap stays off the band as it is off the detector
+            int j = hit[k] ? std::min(lo[k], H - sp.rows) : (below[k] ? H - sp.rows : 0);
+            sp.j0[k] = j;
+            double* A = sp.mats.data() + 12 * (size_t)k;
+            for (int c = 0; c < 4; ++c) A[4 + c] -= (double)j * A[8 + c];
+        }
+        plan.push_back(std::move(sp));
+    }
+    return plan;
+}
+
+fdk_status stream_init(DeviceState& d)
+{
+    if (d.h2d == nullptr) {
+        HIP_TRY(hipStreamCreateWithFlags(&d.h2d, hipStreamNonBlocking));
+        HIP_TRY(hipStreamCreateWithFlags(&d.d2h, hipStreamNonBlocking));
+        for (int b = 0; b < 2; ++b) {
+            HIP_TRY(hipEventCreateWithFlags(&d.band_ready[b], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&d.band_free[b], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&d.slab_done[b], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&d.slab_free[b], hipEventDisableTiming));
+        }
+    }
+    return FDK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fdk_status fdk_backproject_streamed(const fdk_volume* vol, const fdk_projections* proj, float* volume,
+                                    int32_t slab_planes, int32_t flags, int accumulate, void* stream)
+{
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
+    load_env_tuning();
+    fdk_status st = fdk_validate(vol, proj, 1);
+    if (st != FDK_OK) return st;
+    if (volume == nullptr) return fail(FDK_E_INVALID_ARG, "volume buffer is NULL");
+    if (slab_planes < 1) return fail(FDK_E_INVALID_ARG, "slab_planes=%d < 1", slab_planes);
+    if (flags & ~FDK_STREAM_HOST_VOLUME) return fail(FDK_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    const bool host_vol = (flags & FDK_STREAM_HOST_VOLUME) != 0;
+    DeviceState* d = nullptr;
+    if ((st = device_state(&d)) != FDK_OK) return st;
+    if ((st = stream_init(*d)) != FDK_OK) return st;
+    hipStream_t cs = static_cast<hipStream_t>(stream);
+
+    const std::vector<SlabPlan> plan = plan_slabs(vol, proj, slab_planes);
+    const int N = proj->n_proj, W = proj->width, H = proj->height;
+    const size_t es = (size_t)esize_of(proj->dtype);
+    const size_t plane = (size_t)vol->L * vol->L;
+    int max_rows = 1;
+    for (const SlabPlan& sp : plan) max_rows = std::max(max_rows, sp.rows);
+    // every slab's geometry is validated before anything is enqueued
+    for (const SlabPlan& sp : plan) {
+        fdk_volume sv = *vol;
+        sv.z_begin = sp.z0;
+        sv.z_count = sp.nz;
+        fdk_projections bp = *proj;
+        bp.height = sp.rows;
+        bp.mats = sp.mats.data();
+        if ((st = fdk_validate(&sv, &bp, 1)) != FDK_OK) return st;
+    }
+    for (int b = 0; b < 2; ++b) {
+        // buffers about to be reallocated must be idle
+        if (d->band[b].n < (size_t)N * max_rows * W * es ||
+            (host_vol && d->slab[b].n < (size_t)slab_planes * plane * 4))
+            HIP_TRY(hipDeviceSynchronize());
+        hipError_t e = ensure(d->band[b], (size_t)N * max_rows * W * es);
+        if (e == hipSuccess && host_vol) e = ensure(d->slab[b], (size_t)slab_planes * plane * 4);
+        if (e != hipSuccess) return fail(FDK_E_NOMEM, "streaming buffers: %s", hipGetErrorString(e));
+    }
+    const unsigned char* src = static_cast<const unsigned char*>(proj->data);
+    unsigned char* hvol = reinterpret_cast<unsigned char*>(volume);
+
+    auto enqueue_in = [&](size_t s) -> fdk_status {
+        const SlabPlan& sp = plan[s];
+        const int b = (int)(s & 1);
+        if (d->band_used[b]) HIP_TRY(hipStreamWaitEvent(d->h2d, d->band_free[b], 0));
+        unsigned char* dst = static_cast<unsigned char*>(d->band[b].p);
+        const size_t chunk = (size_t)sp.rows * W * es;
+        for (int k = 0; k < N; ++k)
+            HIP_TRY(hipMemcpyAsync(dst + (size_t)k * chunk, src + ((size_t)k * H + sp.j0[k]) * W * es, chunk,
+                                   hipMemcpyDefault, d->h2d));
+        if (host_vol && accumulate) {
+            if (d->slab_used[b]) HIP_TRY(hipStreamWaitEvent(d->h2d, d->slab_free[b], 0));
+            HIP_TRY(hipMemcpyAsync(d->slab[b].p, hvol + (size_t)(sp.z0 - vol->z_begin) * plane * 4,
+                                   (size_t)sp.nz * plane * 4, hipMemcpyDefault, d->h2d));
+        }
+        HIP_TRY(hipEventRecord(d->band_ready[b], d->h2d));
+        return FDK_OK;
+    };
+
+    if ((st = enqueue_in(0)) != FDK_OK) return st;
+    for (size_t s = 0; s < plan.size(); ++s) {
+        if (s + 1 < plan.size() && (st = enqueue_in(s + 1)) != FDK_OK) return st;
+        const SlabPlan& sp = plan[s];
+        const int b = (int)(s & 1);
+        HIP_TRY(hipStreamWaitEvent(cs, d->band_ready[b], 0));
+        if (host_vol && !accumulate && d->slab_used[b]) HIP_TRY(hipStreamWaitEvent(cs, d->slab_free[b], 0));
+        fdk_volume sv = *vol;
+        sv.z_begin = sp.z0;
+        sv.z_count = sp.nz;
+        fdk_projections bp = *proj;
+        bp.height = sp.rows;
+        bp.mats = sp.mats.data();
+        bp.data = d->band[b].p;
+        float* out = host_vol ? static_cast<float*>(d->slab[b].p)
+                              : volume + (size_t)(sp.z0 - vol->z_begin) * plane;
+        if ((st = fdk_backproject(&sv, &bp, out, accumulate, cs)) != FDK_OK) return st;
+        HIP_TRY(hipEventRecord(d->band_free[b], cs));
+        d->band_used[b] = true;
+        if (host_vol) {
+            HIP_TRY(hipEventRecord(d->slab_done[b], cs));
+            HIP_TRY(hipStreamWaitEvent(d->d2h, d->slab_done[b], 0));
+            HIP_TRY(hipMemcpyAsync(hvol + (size_t)(sp.z0 - vol->z_begin) * plane * 4, d->slab[b].p,
+                                   (size_t)sp.nz * plane * 4, hipMemcpyDefault, d->d2h));
+            HIP_TRY(hipEventRecord(d->slab_free[b], d->d2h));
+            d->slab_used[b] = true;
+        }
+    }
+    // the caller's stream completes only when the volume is in place
+    if (host_vol)
+        for (int b = 0; b < 2; ++b)
+            if (d->slab_used[b]) HIP_TRY(hipStreamWaitEvent(cs, d->slab_free[b], 0));
+    return FDK_OK;
+}
+
+fdk_status fdk_streamed_plan(const fdk_volume* vol, const fdk_projections* proj, int32_t slab_planes,
+                             int32_t* n_slabs, int32_t* band_rows, int32_t* first_rows)
+{
+    fdk_status st = fdk_validate(vol, proj, 0);
+    if (st != FDK_OK) return st;
+    if (slab_planes < 1) return fail(FDK_E_INVALID_ARG, "slab_planes=%d < 1", slab_planes);
+    if (n_slabs == nullptr) return fail(FDK_E_INVALID_ARG, "n_slabs is NULL");
+    const std::vector<SlabPlan> plan = plan_slabs(vol, proj, slab_planes);
+    *n_slabs = (int32_t)plan.size();
+    for (size_t s = 0; s < plan.size(); ++s) {
+        if (band_rows) band_rows[s] = plan[s].rows;
+        if (first_rows)
+            std::copy(plan[s].j0.begin(), plan[s].j0.end(), first_rows + s * (size_t)proj->n_proj);
+    }
+    return FDK_OK;
+}
+
 fdk_status fdk_pack_projections(const float* src, int32_t n_proj, int32_t width, int32_t height,
                                 int32_t dtype, void* dst, float* scale_out, void* stream)
 {
@@ -1458,6 +1666,11 @@ fdk_status fdk_release_workspace(void)
     d.filter_cache.clear();
     release(d.filter_ws);
     for (DevBuf* b : {&d.it_p0, &d.it_p1, &d.it_v0, &d.it_v1, &d.it_part, &d.it_st}) release(*b);
+    for (int b = 0; b < 2; ++b) {
+        release(d.band[b]);
+        release(d.slab[b]);
+        d.band_used[b] = d.slab_used[b] = false;
+    }
     d.have_last = false;
     return FDK_OK;
 }

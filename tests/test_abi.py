@@ -279,3 +279,36 @@ def test_solver_validation(fdk):
     assert lib.fdk_cgls(ctypes.byref(v), ctypes.byref(pb), 1, 2, 0, None, None) == -2
     assert lib.fdk_sirt(ctypes.byref(v), ctypes.byref(pb), 1, 2, 1.0, 0, None, None) == -2
     assert b"projection 1" in lib.fdk_last_error()
+
+
+@pytest.mark.parametrize("tilt,H,slab", [(0.0, 72, 5), (3.0, 72, 8), (0.0, 24, 6), (2.0, 24, 40)])
+def test_streamed_plan_covers_every_tap(fdk, tilt, H, slab):
+    """Host-side slab plan of fdk_backproject_streamed: every detector row a
+    voxel of the slab can sample (floor(iy) .. floor(iy) + 1, with a row of
+    slack either side for FP32 coordinates) lies inside the projection's band,
+    and every band lies on the detector, so off-detector taps stay off."""
+    import numpy as np
+    W, L, voxel = 96, 40, 4.0
+    carm = S.CArm(12, W, H, pixel=384.0 / W, tilt_deg=tilt)
+    mats = S.carm_matrices(carm)
+    geom, vol = fdk.Geometry(mats, W, H), fdk.Volume(L, voxel)
+    rows, first = fdk.streamed_plan(geom, vol, slab)
+    assert len(rows) == -(-L // slab)
+    assert np.all(rows >= 1) and np.all(rows <= H)
+    assert np.all(first >= 0) and np.all(first + rows[:, None] <= H)
+    o = S.default_origin(L, voxel)
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    X = np.stack([o[0] + x * voxel, o[1] + y * voxel, o[2] + z * voxel, np.ones(x.shape)], -1)
+    for s in range(len(rows)):
+        P = X[s * slab:(s + 1) * slab].reshape(-1, 4)
+        for k in range(mats.shape[0]):
+            uvw = P @ mats[k].T
+            iy = uvw[:, 1] / uvw[:, 2]
+            j = np.floor(iy)
+            need_lo = np.clip(j - 1, 0, H - 1)
+            need_hi = np.clip(j + 2, 0, H - 1)
+            on = (iy > -2) & (iy < H + 1)
+            assert np.all(need_lo[on] >= first[s, k]), (s, k)
+            assert np.all(need_hi[on] < first[s, k] + rows[s]), (s, k)
+    if H == 24 and slab < L:
+        assert rows.min() < H   # some slab needs only part of the detector
