@@ -248,7 +248,7 @@ int size_class(int L)
 // before the global atomics.
 TileShape default_adjoint_tile(int)
 {
-    return {16, 1, 4};   // detector tiles of 16 rows, one projection per workgroup
+    return {64, 1, 4};   // detector tiles of 64 rows x 320 columns, one projection per workgroup
 }
 
 TileShape default_tile(int L, int dtype)

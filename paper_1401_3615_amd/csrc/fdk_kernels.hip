@@ -974,11 +974,16 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
     const float tlo = (float)(j0 - b.cv), thi = (float)(j1 - b.cv);
     const int64_t plane = (int64_t)b.L * b.L;
     const float zlo = (float)(b.z_begin - b.ctr), zhi = (float)(b.z_begin + b.z_count - 1 - b.ctr);
-    // the workgroup walks 32 x 32 blocks of columns, each wavefront an 8 x 8
-    // patch of them: its samples then spread over >= 21 pixels whatever the
-    // angle, which keeps LDS address conflicts low
+    // the workgroup walks 32 x 32 blocks of columns, each wavefront a 16 x 4
+    // patch of them with its long side along the volume axis that moves the
+    // samples across detector columns (judged from the first projection of
+    // the group at the volume centre): the 64 lanes fall on >= 16 distinct
+    // columns, at most 4 deep along the ray, which keeps same-address LDS
+    // atomics low
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int px = (wave & 3) * 8 + (lane & 7), py = (wave >> 2) * 8 + (lane >> 3);
+    const int pa = (wave & 1) * 16 + (lane & 15), pb = (wave >> 1) * 4 + (lane >> 4);
+    const bool along_x = fabs(coef[0] * coef[11] - coef[3] * coef[8]) >= fabs(coef[1] * coef[11] - coef[3] * coef[9]);
+    const int px = along_x ? pa : pb, py = along_x ? pb : pa;
     const int nbx = (b.L + 31) >> 5, nblk = nbx * nbx;
     for (int blk = 0; blk < nblk; ++blk) {
         const int by = blk / nbx;
@@ -1040,10 +1045,11 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
             oi[p] = (int)fau + b.cu - i0;
             oj[p] = on ? (int)fav + b.cv - j0 : -(1 << 28);
         }
+        // voxel values four planes per step, the next four in flight while the
+        // current ones are scattered (the loads are unconditional, past the
+        // interval from its last plane, so the waits for them can be partial)
         const float* in = b.vol + (int64_t)y * b.L + x;
-        for (int zl = zl_a; zl <= zl_b; ++zl) {
-            const float val0 = in[(int64_t)zl * plane];
-            if (val0 == 0.0f) continue;
+        auto scatter = [&](int zl, float val0) {
             const float t = (float)(zl - zmid);
             const float vs = val0 * b.out_scale;
 #pragma unroll
@@ -1074,6 +1080,21 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
                 if (r1 && c0) __hip_atomic_fetch_add(tl + tw, (double)(bw - bw * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (r1 && c1) __hip_atomic_fetch_add(tl + tw + 1, (double)(bw * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
+        };
+        const float* pz = in + (int64_t)zl_a * plane;   // first plane of the current step
+        const float* plast = in + (int64_t)zl_b * plane;
+        float cur[4], nxt[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cur[j] = *(zl_a + j <= zl_b ? pz + j * plane : plast);
+        for (int z4 = zl_a; z4 <= zl_b; z4 += 4) {
+            pz += 4 * plane;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) nxt[j] = *(z4 + 4 + j <= zl_b ? pz + j * plane : plast);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (z4 + j <= zl_b && cur[j] != 0.0f) scatter(z4 + j, cur[j]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
         }
     }
     __syncthreads();
