@@ -294,9 +294,9 @@ def main() -> int:
     # ---------------------------------------------------------------- out-of-core
     if "streamed" in legs:
         # the 1024^3 volume with the projection stack in pinned host memory: each
-        # 64-plane slab receives only its detector row band over PCIe while the
+        # 128-plane slab receives only its detector row band over PCIe while the
         # previous slab is backprojected; then the volume kept in host memory too
-        L2, vox2, slab = 1024, 0.25, 64
+        L2, vox2, slab = 1024, 0.25, 128
         base = fdk.Volume(L2, vox2)
         host_q = q.cpu().pin_memory()
         rows, _ = fdk.streamed_plan(geom, base, slab)

@@ -346,7 +346,7 @@ struct DeviceState {
     // out-of-core form: double-buffered row-band stacks and volume slabs,
     // a host-to-device and a device-to-host copy stream, and the events that
     // order the buffers between the streams (kept across calls)
-    DevBuf band[2], slab[2];
+    DevBuf band[2], slab[2], band_j0;
     hipStream_t h2d = nullptr, d2h = nullptr;
     hipEvent_t band_ready[2] = {}, band_free[2] = {}, slab_done[2] = {}, slab_free[2] = {};
     bool band_used[2] = {false, false}, slab_used[2] = {false, false};
@@ -1245,6 +1245,23 @@ fdk_status fdk_backproject_streamed(const fdk_volume* vol, const fdk_projections
     }
     const unsigned char* src = static_cast<const unsigned char*>(proj->data);
     unsigned char* hvol = reinterpret_cast<unsigned char*>(volume);
+    // a stack in device memory is gathered by one kernel per slab (the band
+    // offsets in a device table); host memory goes through one DMA copy per band
+    bool dev_src = false;
+    {
+        hipPointerAttribute_t attr{};
+        if (hipPointerGetAttributes(&attr, proj->data) == hipSuccess) dev_src = attr.type == hipMemoryTypeDevice;
+        (void)hipGetLastError();
+    }
+    if (dev_src) {
+        std::vector<int32_t> j0s;
+        j0s.reserve(plan.size() * (size_t)N);
+        for (const SlabPlan& sp : plan) j0s.insert(j0s.end(), sp.j0.begin(), sp.j0.end());
+        HIP_TRY(hipStreamSynchronize(d->h2d));   // earlier gathers may still read the table
+        hipError_t e = ensure(d->band_j0, j0s.size() * sizeof(int32_t));
+        if (e != hipSuccess) return fail(FDK_E_NOMEM, "band table: %s", hipGetErrorString(e));
+        HIP_TRY(hipMemcpy(d->band_j0.p, j0s.data(), j0s.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
 
     auto enqueue_in = [&](size_t s) -> fdk_status {
         const SlabPlan& sp = plan[s];
@@ -1252,9 +1269,14 @@ fdk_status fdk_backproject_streamed(const fdk_volume* vol, const fdk_projections
         if (d->band_used[b]) HIP_TRY(hipStreamWaitEvent(d->h2d, d->band_free[b], 0));
         unsigned char* dst = static_cast<unsigned char*>(d->band[b].p);
         const size_t chunk = (size_t)sp.rows * W * es;
-        for (int k = 0; k < N; ++k)
-            HIP_TRY(hipMemcpyAsync(dst + (size_t)k * chunk, src + ((size_t)k * H + sp.j0[k]) * W * es, chunk,
-                                   hipMemcpyDefault, d->h2d));
+        if (dev_src) {
+            HIP_TRY(launch_band_gather(src, dst, static_cast<const int32_t*>(d->band_j0.p) + s * (size_t)N, N, H,
+                                       sp.rows, (int64_t)W * (int64_t)es, d->h2d));
+        } else {
+            for (int k = 0; k < N; ++k)
+                HIP_TRY(hipMemcpyAsync(dst + (size_t)k * chunk, src + ((size_t)k * H + sp.j0[k]) * W * es, chunk,
+                                       hipMemcpyDefault, d->h2d));
+        }
         if (host_vol && accumulate) {
             if (d->slab_used[b]) HIP_TRY(hipStreamWaitEvent(d->h2d, d->slab_free[b], 0));
             HIP_TRY(hipMemcpyAsync(d->slab[b].p, hvol + (size_t)(sp.z0 - vol->z_begin) * plane * 4,
@@ -1671,6 +1693,7 @@ fdk_status fdk_release_workspace(void)
         release(d.slab[b]);
         d.band_used[b] = d.slab_used[b] = false;
     }
+    release(d.band_j0);
     d.have_last = false;
     return FDK_OK;
 }

@@ -127,6 +127,10 @@ hipError_t launch_bp_batched(const TileArgs* dev_scans, const int32_t* dev_item_
                              hipStream_t s);
 hipError_t launch_reset_counter(unsigned* counter, hipStream_t s);
 hipError_t launch_fill(float* p, uint64_t n, float value, hipStream_t s);
+// rows [j0[k], j0[k] + rows) of each of n device images of H rows of row_bytes
+// (even) bytes, packed into n x rows rows
+hipError_t launch_band_gather(const void* src, void* dst, const int32_t* j0, int n, int H, int rows,
+                              int64_t row_bytes, hipStream_t s);
 hipError_t launch_unstage_add(const float* padded, float* out, int n, int W, int H, int Wp,
                               uint64_t stride_elems, int accumulate, hipStream_t s);
 hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* dst, float* scale,

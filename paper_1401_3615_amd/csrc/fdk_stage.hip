@@ -222,7 +222,40 @@ __global__ void zero_u32_kernel(unsigned* p, int n)
     if (k < n) p[k] = 0u;
 }
 
+// Row bands of a device-resident stack (out-of-core form): band row r of
+// projection k is source row j0[k] + r.  One workgroup per band row.
+template <typename U>
+__global__ __launch_bounds__(256) void band_gather_kernel(const U* __restrict__ src, U* __restrict__ dst,
+                                                          const int32_t* __restrict__ j0, int H, int rows,
+                                                          int row_units)
+{
+    const int64_t row = blockIdx.x;
+    const int k = (int)(row / rows), r = (int)(row - (int64_t)k * rows);
+    const U* from = src + ((int64_t)k * H + j0[k] + r) * row_units;
+    U* to = dst + row * row_units;
+    for (int i = threadIdx.x; i < row_units; i += blockDim.x) to[i] = from[i];
+}
+
 }  // namespace
+
+hipError_t launch_band_gather(const void* src, void* dst, const int32_t* j0, int n, int H, int rows,
+                              int64_t row_bytes, hipStream_t s)
+{
+    const int64_t blocks = (int64_t)n * rows;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const uintptr_t a = (uintptr_t)src | (uintptr_t)dst | (uintptr_t)row_bytes;
+    if (a % 16 == 0)
+        band_gather_kernel<uint4><<<(unsigned)blocks, 256, 0, s>>>((const uint4*)src, (uint4*)dst, j0, H, rows,
+                                                                   (int)(row_bytes / 16));
+    else if (a % 4 == 0)
+        band_gather_kernel<uint32_t><<<(unsigned)blocks, 256, 0, s>>>((const uint32_t*)src, (uint32_t*)dst, j0, H,
+                                                                      rows, (int)(row_bytes / 4));
+    else
+        band_gather_kernel<uint16_t><<<(unsigned)blocks, 256, 0, s>>>((const uint16_t*)src, (uint16_t*)dst, j0, H,
+                                                                      rows, (int)(row_bytes / 2));
+    return hipGetLastError();
+}
 
 hipError_t launch_stage(const StageArgs& a, hipStream_t s)
 {

@@ -23,6 +23,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 from collections import defaultdict
 
@@ -64,8 +65,16 @@ def read_stats(path: str) -> list[dict]:
     return rows
 
 
-def stats_markdown(path: str, top: int = 15) -> str:
-    rows = sorted(read_stats(path), key=lambda r: -r["total_ns"])[:top]
+# kernels of this library (the rest of a trace is torch's input generation)
+OWN_KERNELS = r"^(bp_|fp_|window_kernel|stage_|fold_|filter_kernel|unstage|absmax|convert|finalize|zero_u32|fill|"\
+              r"reset_counter|sumsq|max_kernel|scalar_kernel|cgls_|residual_kernel|sirt_|inv_floor)"
+
+
+def stats_markdown(path: str, top: int = 15, match: str | None = None) -> str:
+    rows = read_stats(path)
+    if match:
+        rows = [r for r in rows if re.search(match, short_name(r["name"]))]
+    rows = sorted(rows, key=lambda r: -r["total_ns"])[:top]
     out = ["| kernel | calls | avg ms | min ms | max ms | total ms | % |", "|---|---:|---:|---:|---:|---:|---:|"]
     for r in rows:
         out.append(f"| `{short_name(r['name'])}` | {r['calls']} | {r['avg_ns'] / 1e6:.3f} | "
@@ -119,6 +128,7 @@ def main(argv=None) -> int:
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=15)
+    s.add_argument("--own", action="store_true", help="only kernels of this library")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -131,7 +141,7 @@ def main(argv=None) -> int:
     c.add_argument("--kernel", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
-        print(stats_markdown(a.csv, a.top))
+        print(stats_markdown(a.csv, a.top, OWN_KERNELS if a.own else None))
     elif a.cmd == "traffic":
         res = traffic(a.fetch, a.write, a.kernel, a.copy, a.copy_bytes)
         txt = json.dumps(res, indent=1)

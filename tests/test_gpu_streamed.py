@@ -96,6 +96,21 @@ def test_streamed_slab_of_a_slab_and_fp16(fdk):
     assert oracle.rel_l2(got.cpu().numpy(), inc) <= 1e-6
 
 
+@pytest.mark.parametrize("W", [97, 98, 96])
+def test_streamed_device_stack_row_widths(fdk, W):
+    """Device-resident FP16 stacks are gathered into bands by a kernel that
+    copies rows in 2-, 4- or 16-byte units depending on the row length."""
+    carm = S.CArm(10, W, 48, pixel=384.0 / W, tilt_deg=1.0)
+    mats = S.carm_matrices(carm)
+    proj = torch.from_numpy(S.random_projections(10, 48, W, 6))
+    geom, vol = fdk.Geometry(mats, W, 48), fdk.Volume(30, 4.0)
+    packed, scale = fdk.pack_projections(proj.to(DEV), torch.float16)
+    inc = _incore(fdk, packed, geom, vol, scale=scale)
+    got = fdk.backproject_streamed(packed, geom, vol, 4, scale=scale)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(got.cpu().numpy(), inc) <= 1e-6
+
+
 def test_streamed_buffers_grow_between_calls(fdk):
     mats, proj = _case(seed=5)
     geom = fdk.Geometry(mats, 96, 48)
