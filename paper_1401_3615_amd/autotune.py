@@ -35,7 +35,7 @@ from . import (F16, F32, BF16, TUNE_ADJOINT, TUNE_BATCHED, FdkError, Geometry, V
 BP_STRIPS = (2, 4, 8, 16, 32)
 BP_WAVES = (1, 2, 4)
 BP_LAYOUTS = (0, 1, 2, 3)
-ADJ_SHAPES = [(r, g, 4) for r in (8, 16, 32, 64) for g in (1, 2, 4)] + [(8, 2, 0), (16, 4, 0)]
+ADJ_SHAPES = [(r, g, 4) for r in (12, 28, 60) for g in (1, 2, 4)] + [(8, 2, 0), (16, 4, 0)]
 
 
 @dataclass

@@ -248,7 +248,7 @@ int size_class(int L)
 // before the global atomics.
 TileShape default_adjoint_tile(int)
 {
-    return {64, 1, 4};   // detector tiles of 64 rows x 320 columns, one projection per workgroup
+    return {60, 1, 4};   // detector tiles of 60 rows x 316 columns, one projection per workgroup
 }
 
 TileShape default_tile(int L, int dtype)
@@ -480,7 +480,9 @@ TileShape pick_tile(int L, int dtype)
 bool valid_shape(int slot, TileShape t)
 {
     if (slot == kAdjointSlot) {
-        if (t.layout == 4) return t.strip >= 1 && t.strip * t.waves <= kBandCap && supported_band_group(t.waves);
+        if (t.layout == 4)   // at least one column per tile
+            return t.strip >= 1 && (int64_t)(t.strip + 2 * kBandBorder) * (1 + 2 * kBandBorder) * t.waves <= kBandCap &&
+                   supported_band_group(t.waves);
         return t.layout == 0 && supported_tile(t.strip, t.waves) != 0;
     }
     return t.layout >= 0 && t.layout <= 3 && supported_tile(t.strip, t.waves) != 0;
@@ -668,7 +670,7 @@ static fdk_status forwardproject_tiles(const fdk_volume* vol, const float* volum
     fdk_status st;
     BandArgs b{};
     b.th = std::min(t.strip, geom->height);
-    b.tw = std::min(geom->width, kBandCap / (b.th * t.waves));
+    b.tw = std::min(geom->width, kBandCap / ((b.th + 2 * kBandBorder) * t.waves) - 2 * kBandBorder);
     b.tiles_u = (geom->width + b.tw - 1) / b.tw;
     b.tiles_v = (geom->height + b.th - 1) / b.th;
     if ((int64_t)b.tiles_u * b.tiles_v * ((geom->n_proj + t.waves - 1) / t.waves) > 0x7fffffffLL)

@@ -67,10 +67,12 @@ struct BandArgs {
     int32_t const_w;             // 1: w does not depend on z for any projection
 };
 
-// group = projections per workgroup (1, 2, 4 or 8); P tw th <= kBandCap
+// group = projections per workgroup (1, 2, 4 or 8); P (tw + 2 kBandBorder)
+// (th + 2 kBandBorder) <= kBandCap
 hipError_t launch_fp_band(const BandArgs& b, int group, hipStream_t s);
 int supported_band_group(int group);
 constexpr int kBandCap = 20480;   // FP64 accumulators of one workgroup's detector tiles (160 KiB of LDS)
+constexpr int kBandBorder = 2;    // border pixels around each tile that absorb off-tile taps
 
 // FDK preprocessing: weights and ramp filtering of every row (fdk_filter.hip).
 struct FilterArgs {

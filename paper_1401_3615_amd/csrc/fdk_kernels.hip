@@ -956,7 +956,9 @@ __device__ __forceinline__ BandCol band_interval(float u0, float v0, float w0, f
 template <int P, bool CW>
 __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
 {
-    extern __shared__ double lds[];   // P tiles of tw x th, FP64 accumulators
+    // P tiles of FP64 accumulators, each th x tw pixels inside a border of
+    // kBandBorder pixels that absorbs the taps falling just off the tile
+    extern __shared__ double lds[];
     const int groups = (b.n_proj + P - 1) / P;
     // group-minor order: concurrently resident workgroups share the planes of
     // one band of detector rows
@@ -965,8 +967,9 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
     const int tu = tile % b.tiles_u, tv = tile / b.tiles_u;
     const int i0 = tu * b.tw, i1 = min(i0 + b.tw, b.W);
     const int j0 = tv * b.th, j1 = min(j0 + b.th, b.H);
-    const int tw = i1 - i0, th = j1 - j0, tpx = tw * th;
-    for (int e = threadIdx.x; e < P * tpx; e += kBandThreads) lds[e] = 0.0;
+    const int tw = i1 - i0, th = j1 - j0;
+    const int tp = tw + 2 * kBandBorder, tsz = tp * (th + 2 * kBandBorder);   // pitch, size of one tile
+    for (int e = threadIdx.x; e < P * tsz; e += kBandThreads) lds[e] = 0.0;
     __syncthreads();
     const double* coef = b.coef + 16 * k0;
     // the tile in centred detector coordinates
@@ -1033,12 +1036,12 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
             swb[p] = wf;
             sdu[p] = (float)fma(-(double)fau, c[10], c[2]);
             sdv[p] = (float)fma(-(double)fav, c[10], c[6]);
-            if (CW) {   // u/w and v/w themselves step linearly; swb holds 1/w^2
+            if (CW) {   // u/w and v/w themselves step linearly; swb holds out_scale / w^2
                 sub[p] *= rf;
                 svb[p] *= rf;
                 sdu[p] *= rf;
                 sdv[p] *= rf;
-                swb[p] = rf * rf;
+                swb[p] = rf * rf * b.out_scale;
             }
             // tap (i, j) relative to the tile; an inactive projection gets a
             // row offset that keeps every tap outside
@@ -1049,9 +1052,9 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
         // current ones are scattered (the loads are unconditional, past the
         // interval from its last plane, so the waits for them can be partial)
         const float* in = b.vol + (int64_t)y * b.L + x;
-        auto scatter = [&](int zl, float val0) {
-            const float t = (float)(zl - zmid);
-            const float vs = val0 * b.out_scale;
+        // t: plane offset from the anchor plane
+        auto scatter = [&](float t, float val0) {
+            const float vs = CW ? val0 : val0 * b.out_scale;   // CW: the scale is in swb
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const double* c = coef + 16 * p;
@@ -1071,14 +1074,16 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
                 const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
                 const int ti = oi[p] + cvt_floor(dx), tj = oj[p] + cvt_floor(dy);
                 const float val = vs * wgt;
-                const float bw = val * sy, tp = val - bw;
-                const bool c0 = (unsigned)ti < (unsigned)tw, c1 = (unsigned)(ti + 1) < (unsigned)tw;
-                const bool r0 = (unsigned)tj < (unsigned)th, r1 = (unsigned)(tj + 1) < (unsigned)th;
-                double* tl = lds + p * tpx + __mul24(tj, tw) + ti;
-                if (r0 && c0) __hip_atomic_fetch_add(tl, (double)(tp - tp * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (r0 && c1) __hip_atomic_fetch_add(tl + 1, (double)(tp * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (r1 && c0) __hip_atomic_fetch_add(tl + tw, (double)(bw - bw * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (r1 && c1) __hip_atomic_fetch_add(tl + tw + 1, (double)(bw * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const float bw = val * sy, tv = val - bw;
+                // a tap pair off the tile is clamped into the border, where
+                // both taps stay (the border is never written back)
+                const int ci = min(max(ti, -kBandBorder), tw);
+                const int cj = min(max(tj, -kBandBorder), th);
+                double* tl = lds + (p * tsz + kBandBorder * tp + kBandBorder) + __mul24(cj, tp) + ci;
+                __hip_atomic_fetch_add(tl, (double)(tv - tv * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(tl + 1, (double)(tv * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(tl + tp, (double)(bw - bw * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(tl + tp + 1, (double)(bw * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         };
         const float* pz = in + (int64_t)zl_a * plane;   // first plane of the current step
@@ -1090,9 +1095,10 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
             pz += 4 * plane;
 #pragma unroll
             for (int j = 0; j < 4; ++j) nxt[j] = *(z4 + 4 + j <= zl_b ? pz + j * plane : plast);
+            const float tz = (float)(z4 - zmid);
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (z4 + j <= zl_b && cur[j] != 0.0f) scatter(z4 + j, cur[j]);
+                if (z4 + j <= zl_b && cur[j] != 0.0f) scatter(tz + (float)j, cur[j]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
         }
@@ -1100,11 +1106,12 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
     __syncthreads();
     for (int p = 0; p < np; ++p) {
         float* out = b.out + ((int64_t)(k0 + p) * b.H + j0) * b.W + i0;
-        const double* src = lds + p * tpx;
-        for (int e = threadIdx.x; e < tpx; e += kBandThreads) {
+        const double* src = lds + p * tsz + kBandBorder * tp + kBandBorder;
+        for (int e = threadIdx.x; e < tw * th; e += kBandThreads) {
             const int r = e / tw, cl = e - r * tw;
             float* d = out + (int64_t)r * b.W + cl;
-            *d = b.accumulate ? (float)(src[e] + (double)*d) : (float)src[e];
+            const double v = src[r * tp + cl];
+            *d = b.accumulate ? (float)(v + (double)*d) : (float)v;
         }
     }
 }
@@ -1266,7 +1273,7 @@ static hipError_t launch_band(const BandArgs& b, hipStream_t s)
 {
     const int groups = (b.n_proj + P - 1) / P;
     const int64_t blocks = (int64_t)b.tiles_u * b.tiles_v * groups;
-    const size_t lds = (size_t)P * b.tw * b.th * sizeof(double);
+    const size_t lds = (size_t)P * (b.tw + 2 * kBandBorder) * (b.th + 2 * kBandBorder) * sizeof(double);
     if (blocks > 0x7fffffffLL || lds > (size_t)kBandCap * sizeof(double)) return hipErrorInvalidValue;
     static bool attr_set = false;
     if (!attr_set) {

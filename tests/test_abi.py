@@ -176,15 +176,15 @@ def test_tiles_and_tuning_file(fdk, tmp_path):
 
 def test_adjoint_tiles(fdk):
     vol = fdk.Volume(256, 1.0)
-    assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == (64, 1, 4)
-    for bad in [(16, 3, 4), (4096, 8, 4), (0, 1, 4), (16, 4, 3), (16, 4, 1), (5, 1, 0)]:
+    assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == (60, 1, 4)
+    for bad in [(16, 3, 4), (509, 8, 4), (0, 1, 4), (16, 4, 3), (16, 4, 1), (5, 1, 0)]:
         with pytest.raises(fdk.FdkError):
             fdk.set_tile(fdk.TUNE_ADJOINT, *bad)
-    for good in [(1, 1, 4), (2560, 8, 4), (8, 2, 0)]:
+    for good in [(1, 1, 4), (508, 8, 4), (4092, 1, 4), (8, 2, 0)]:
         fdk.set_tile(fdk.TUNE_ADJOINT, *good)
         assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == good
     fdk.set_tile(fdk.TUNE_ADJOINT, 0, 0)
-    assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == (64, 1, 4)
+    assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == (60, 1, 4)
 
 
 def test_batched_slot(fdk):

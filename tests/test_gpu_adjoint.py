@@ -38,7 +38,7 @@ def test_forwardproject_matches_oracle(fdk):
 
 
 @pytest.mark.parametrize("strip,waves,layout", [(2, 1, 0), (8, 2, 0), (16, 4, 0), (32, 4, 0),
-                                                (1, 1, 4), (5, 2, 4), (13, 4, 4), (16, 1, 4), (64, 1, 4), (77, 8, 4)])
+                                                (1, 1, 4), (5, 2, 4), (13, 4, 4), (16, 1, 4), (60, 1, 4), (77, 8, 4), (508, 8, 4)])
 def test_forwardproject_every_shape(fdk, strip, waves, layout):
     """Ragged grid (L = 37): direct global scatter for several strip shapes
     and detector tiles of 1 to 77 rows for 1 to 8 projections per
