@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <initializer_list>
+
 #include "fdk_internal.h"
 
 namespace fdk {
@@ -35,12 +37,28 @@ __device__ __forceinline__ double block_reduce(double v, double* sh)
     return t;
 }
 
+// The element loops below take four elements per load (float4) when VEC is
+// set (every operand 16-byte aligned), then the remainder one by one.
+template <bool VEC>
 __global__ void __launch_bounds__(kT) sumsq_kernel(const float* __restrict__ a, int64_t n,
                                                    double* __restrict__ part)
 {
     __shared__ double sh[kT / kWave];
+    const int64_t t0 = (int64_t)blockIdx.x * kT + threadIdx.x, stride = (int64_t)kRedBlocks * kT;
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kT) {
+    int64_t done = 0;
+    if (VEC) {
+        const float4* a4 = reinterpret_cast<const float4*>(a);
+        for (int64_t i = t0; i < (n >> 2); i += stride) {
+            const float4 v = a4[i];
+            acc = fma((double)v.x, (double)v.x, acc);
+            acc = fma((double)v.y, (double)v.y, acc);
+            acc = fma((double)v.z, (double)v.z, acc);
+            acc = fma((double)v.w, (double)v.w, acc);
+        }
+        done = n & ~(int64_t)3;
+    }
+    for (int64_t i = done + t0; i < n; i += stride) {
         const double x = a[i];
         acc = fma(x, x, acc);
     }
@@ -88,8 +106,11 @@ __global__ void __launch_bounds__(kT) scalar_kernel(const double* __restrict__ p
     }
 }
 
-// x += alpha d over the volume and r -= alpha q over the projections (one
-// index space of nv + np elements); the partial sums of the new ||r||^2.
+// x += alpha d over the volume and r -= alpha q over the projections; the
+// partial sums of the new ||r||^2.
+__device__ __forceinline__ float axpy1(double a, float y, float x) { return (float)fma(a, (double)y, (double)x); }
+
+template <bool VEC>
 __global__ void __launch_bounds__(kT) cgls_update_kernel(float* __restrict__ x, const float* __restrict__ d,
                                                          int64_t nv, float* __restrict__ r,
                                                          const float* __restrict__ q, int64_t np,
@@ -98,17 +119,40 @@ __global__ void __launch_bounds__(kT) cgls_update_kernel(float* __restrict__ x, 
 {
     __shared__ double sh[kT / kWave];
     const double alpha = st[kStAlpha];
-    double acc = 0.0;
-    const int64_t n = nv + np;
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kT) {
-        if (i < nv) {
-            x[i] = (float)fma(alpha, (double)d[i], (double)x[i]);
-        } else {
-            const int64_t j = i - nv;
-            const float rn = (float)fma(-alpha, (double)q[j], (double)r[j]);
-            r[j] = rn;
-            acc = fma((double)rn, (double)rn, acc);
+    const int64_t t0 = (int64_t)blockIdx.x * kT + threadIdx.x, stride = (int64_t)kRedBlocks * kT;
+    int64_t done = 0;
+    if (VEC) {
+        float4* x4 = reinterpret_cast<float4*>(x);
+        const float4* d4 = reinterpret_cast<const float4*>(d);
+        for (int64_t i = t0; i < (nv >> 2); i += stride) {
+            const float4 a = x4[i], b = d4[i];
+            x4[i] = make_float4(axpy1(alpha, b.x, a.x), axpy1(alpha, b.y, a.y), axpy1(alpha, b.z, a.z),
+                                axpy1(alpha, b.w, a.w));
         }
+        done = nv & ~(int64_t)3;
+    }
+    for (int64_t i = done + t0; i < nv; i += stride) x[i] = axpy1(alpha, d[i], x[i]);
+    double acc = 0.0;
+    done = 0;
+    if (VEC) {
+        float4* r4 = reinterpret_cast<float4*>(r);
+        const float4* q4 = reinterpret_cast<const float4*>(q);
+        for (int64_t i = t0; i < (np >> 2); i += stride) {
+            const float4 a = r4[i], b = q4[i];
+            const float4 o = make_float4(axpy1(-alpha, b.x, a.x), axpy1(-alpha, b.y, a.y), axpy1(-alpha, b.z, a.z),
+                                         axpy1(-alpha, b.w, a.w));
+            r4[i] = o;
+            acc = fma((double)o.x, (double)o.x, acc);
+            acc = fma((double)o.y, (double)o.y, acc);
+            acc = fma((double)o.z, (double)o.z, acc);
+            acc = fma((double)o.w, (double)o.w, acc);
+        }
+        done = np & ~(int64_t)3;
+    }
+    for (int64_t i = done + t0; i < np; i += stride) {
+        const float rn = axpy1(-alpha, q[i], r[i]);
+        r[i] = rn;
+        acc = fma((double)rn, (double)rn, acc);
     }
     const double t = block_reduce<false>(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -124,17 +168,31 @@ __global__ void __launch_bounds__(kT) cgls_direction_kernel(float* __restrict__ 
 }
 
 // e = p - r;  partial sums of ||e||^2;  r = e (or e * w when w is given)
+template <bool VEC>
 __global__ void __launch_bounds__(kT) residual_kernel(float* __restrict__ r, const float* __restrict__ p,
                                                       const float* __restrict__ w, int64_t n,
                                                       double* __restrict__ part)
 {
     __shared__ double sh[kT / kWave];
+    const int64_t t0 = (int64_t)blockIdx.x * kT + threadIdx.x, stride = (int64_t)kRedBlocks * kT;
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kT) {
-        const double e = (double)p[i] - (double)r[i];
+    int64_t done = 0;
+    auto one = [&](float rv, float pv, float wv) {
+        const double e = (double)pv - (double)rv;
         acc = fma(e, e, acc);
-        r[i] = (float)(w ? e * (double)w[i] : e);
+        return (float)(w ? e * (double)wv : e);
+    };
+    if (VEC) {
+        float4* r4 = reinterpret_cast<float4*>(r);
+        const float4* p4 = reinterpret_cast<const float4*>(p);
+        const float4* w4 = reinterpret_cast<const float4*>(w);
+        for (int64_t i = t0; i < (n >> 2); i += stride) {
+            const float4 a = r4[i], b = p4[i], c = w ? w4[i] : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+            r4[i] = make_float4(one(a.x, b.x, c.x), one(a.y, b.y, c.y), one(a.z, b.z, c.z), one(a.w, b.w, c.w));
+        }
+        done = n & ~(int64_t)3;
     }
+    for (int64_t i = done + t0; i < n; i += stride) r[i] = one(r[i], p[i], w ? w[i] : 1.0f);
     const double t = block_reduce<false>(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -169,9 +227,19 @@ unsigned ew_grid(int64_t n)
 
 }  // namespace
 
+static bool aligned16(std::initializer_list<const void*> ptrs)
+{
+    for (const void* p : ptrs)
+        if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return false;
+    return true;
+}
+
 hipError_t launch_sumsq(const float* a, int64_t n, double* part, hipStream_t s)
 {
-    sumsq_kernel<<<kRedBlocks, kT, 0, s>>>(a, n, part);
+    if (aligned16({a}))
+        sumsq_kernel<true><<<kRedBlocks, kT, 0, s>>>(a, n, part);
+    else
+        sumsq_kernel<false><<<kRedBlocks, kT, 0, s>>>(a, n, part);
     return hipGetLastError();
 }
 
@@ -190,7 +258,10 @@ hipError_t launch_scalar(const double* part, double* st, double* hist, int op, i
 hipError_t launch_cgls_update(float* x, const float* d, int64_t nv, float* r, const float* q, int64_t np,
                               const double* st, double* part, hipStream_t s)
 {
-    cgls_update_kernel<<<kRedBlocks, kT, 0, s>>>(x, d, nv, r, q, np, st, part);
+    if (aligned16({x, d, r, q}))
+        cgls_update_kernel<true><<<kRedBlocks, kT, 0, s>>>(x, d, nv, r, q, np, st, part);
+    else
+        cgls_update_kernel<false><<<kRedBlocks, kT, 0, s>>>(x, d, nv, r, q, np, st, part);
     return hipGetLastError();
 }
 
@@ -202,7 +273,10 @@ hipError_t launch_cgls_direction(float* d, const float* sv, int64_t n, const dou
 
 hipError_t launch_residual(float* r, const float* p, const float* w, int64_t n, double* part, hipStream_t s)
 {
-    residual_kernel<<<kRedBlocks, kT, 0, s>>>(r, p, w, n, part);
+    if (aligned16({r, p, w}))
+        residual_kernel<true><<<kRedBlocks, kT, 0, s>>>(r, p, w, n, part);
+    else
+        residual_kernel<false><<<kRedBlocks, kT, 0, s>>>(r, p, w, n, part);
     return hipGetLastError();
 }
 
