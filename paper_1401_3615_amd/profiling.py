@@ -67,7 +67,7 @@ def read_stats(path: str) -> list[dict]:
 
 # kernels of this library (the rest of a trace is torch's input generation)
 OWN_KERNELS = r"^(bp_|fp_|window_kernel|stage_|fold_|filter_kernel|unstage|absmax|convert|finalize|zero_u32|fill|"\
-              r"reset_counter|sumsq|max_kernel|scalar_kernel|cgls_|residual_kernel|sirt_|inv_floor)"
+              r"reset_counter|sumsq|max_kernel|scalar_kernel|cgls_|residual_kernel|sirt_|inv_floor|band_gather)"
 
 
 def stats_markdown(path: str, top: int = 15, match: str | None = None) -> str:
