@@ -328,6 +328,16 @@ int32_t fdk_load_tuning(const char* path);
 fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip, int32_t waves,
                                 int32_t layout);
 
+/* Matrix normalisation (host only): rescales each row-major 3x4 matrix of
+ * mats (HOST, n_proj * 12 doubles, in place) by s = +-1 / ||A[2][0:3]|| so
+ * that w becomes the signed distance along the principal ray (in the units of
+ * the world coordinates, mm) and w > 0 at the world origin, the isocentre.
+ * u/w and v/w are unchanged; the 1/w^2 weight then depends on the
+ * geometry only through distances (Sec. "RabbitCT Benchmarking Framework":
+ * w approximates the distance to the source).  FDK_E_INVALID_ARG for NULL,
+ * n_proj < 1, non-finite entries, a zero third row or w = 0 at the origin. */
+fdk_status fdk_normalize_matrices(double* mats, int32_t n_proj);
+
 /* Host-side check of a call's arguments: the validation fdk_backproject
  * performs, without touching the GPU. */
 fdk_status fdk_validate(const fdk_volume* vol, const fdk_projections* proj,

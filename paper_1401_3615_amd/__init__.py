@@ -25,7 +25,7 @@ __all__ = [
     "forwardproject", "backproject_batched", "pack_projections", "set_tile", "get_tile",
     "load_tuning", "set_tuning_entry", "validate", "release_workspace", "abi_version",
     "BackProject", "ForwardProject", "Scan", "profile_enable", "profile_read", "FilterGeometry",
-    "filter_projections", "cgls", "sirt", "backproject_streamed", "streamed_plan",
+    "filter_projections", "cgls", "sirt", "backproject_streamed", "streamed_plan", "normalize_matrices",
 ]
 
 F32, F16, BF16 = 0, 1, 2
@@ -86,6 +86,7 @@ def load():
         "fdk_load_tuning": ([ctypes.c_char_p], i32),
         "fdk_set_tuning_entry": ([i32, i32, i32, i32, i32], ctypes.c_int),
         "fdk_validate": ([pv, pp, ctypes.c_int], ctypes.c_int),
+        "fdk_normalize_matrices": ([ctypes.POINTER(ctypes.c_double), i32], ctypes.c_int),
         "fdk_release_workspace": ([], ctypes.c_int),
         "fdk_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "fdk_last_error": ([], ctypes.c_char_p),
@@ -467,6 +468,14 @@ def validate(geom: Geometry, vol: Volume, need_data: bool = False, dtype: int = 
     v = vol.c()
     p = geom.c(1 if need_data else None, dtype)
     _check(load().fdk_validate(ctypes.byref(v), ctypes.byref(p), int(need_data)))
+
+
+def normalize_matrices(mats) -> np.ndarray:
+    """fdk_normalize_matrices on a copy: (N, 3, 4) float64 matrices scaled so
+    that ||A[2, :3]|| = 1 and w > 0 at the origin."""
+    m = np.array(mats, dtype=np.float64, copy=True).reshape(-1, 12)
+    _check(load().fdk_normalize_matrices(m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), m.shape[0]))
+    return m.reshape(-1, 3, 4)
 
 
 def release_workspace() -> None:

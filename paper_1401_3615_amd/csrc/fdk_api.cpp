@@ -598,6 +598,28 @@ const char* fdk_status_string(fdk_status st)
 
 const char* fdk_last_error(void) { return g_last_error.c_str(); }
 
+fdk_status fdk_normalize_matrices(double* mats, int32_t n_proj)
+{
+    g_last_error.clear();
+    if (mats == nullptr) return fail(FDK_E_INVALID_ARG, "mats is NULL");
+    if (n_proj < 1) return fail(FDK_E_INVALID_ARG, "n_proj=%d < 1", n_proj);
+    for (int64_t i = 0; i < (int64_t)n_proj * 12; ++i)
+        if (!std::isfinite(mats[i])) return fail(FDK_E_INVALID_ARG, "matrix %lld has a non-finite entry", (long long)(i / 12));
+    for (int k = 0; k < n_proj; ++k) {
+        const double* A = mats + 12 * (size_t)k;
+        const double n = std::sqrt(A[8] * A[8] + A[9] * A[9] + A[10] * A[10]);
+        if (!(n > 0.0)) return fail(FDK_E_INVALID_ARG, "matrix %d: third row has no direction", k);
+        if (A[11] == 0.0) return fail(FDK_E_INVALID_ARG, "matrix %d: w = 0 at the origin", k);
+    }
+    for (int k = 0; k < n_proj; ++k) {
+        double* A = mats + 12 * (size_t)k;
+        const double n = std::sqrt(A[8] * A[8] + A[9] * A[9] + A[10] * A[10]);
+        const double s = (A[11] > 0.0 ? 1.0 : -1.0) / n;
+        for (int i = 0; i < 12; ++i) A[i] *= s;
+    }
+    return FDK_OK;
+}
+
 fdk_status fdk_validate(const fdk_volume* vol, const fdk_projections* proj, int need_data)
 {
     g_last_error.clear();

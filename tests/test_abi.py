@@ -312,3 +312,29 @@ def test_streamed_plan_covers_every_tap(fdk, tilt, H, slab):
             assert np.all(need_hi[on] < first[s, k] + rows[s]), (s, k)
     if H == 24 and slab < L:
         assert rows.min() < H   # some slab needs only part of the detector
+
+
+def test_normalize_matrices(fdk):
+    """Host-side: unit third row, w > 0 at the origin, projected positions
+    unchanged; invalid inputs rejected."""
+    import numpy as np
+    mats, W, H = _case()
+    rng = np.random.default_rng(3)
+    scaled = mats * rng.uniform(-5.0, 5.0, size=(mats.shape[0], 1, 1))
+    scaled[scaled[:, 2, 3] > 0] *= -1.0          # some with w < 0 at the origin
+    out = fdk.normalize_matrices(scaled)
+    np.testing.assert_allclose(np.linalg.norm(out[:, 2, :3], axis=1), 1.0, rtol=1e-15)
+    assert np.all(out[:, 2, 3] > 0)
+    X = np.concatenate([rng.normal(size=(20, 3)) * 4.0, np.ones((20, 1))], 1)
+    for k in range(mats.shape[0]):
+        a, b = X @ scaled[k].T, X @ out[k].T
+        np.testing.assert_allclose(b[:, :2] / b[:, 2:], a[:, :2] / a[:, 2:], rtol=1e-12)
+    np.testing.assert_allclose(out, fdk.normalize_matrices(mats), rtol=1e-13, atol=1e-13)
+    bad = mats.copy()
+    bad[1, 2, :3] = 0.0
+    with pytest.raises(fdk.FdkError):
+        fdk.normalize_matrices(bad)
+    bad = mats.copy()
+    bad[0, 0, 0] = float("nan")
+    with pytest.raises(fdk.FdkError):
+        fdk.normalize_matrices(bad)
