@@ -67,9 +67,25 @@ __device__ __forceinline__ void stage_row(const StageArgs& a, int64_t local_row)
     if (a.esize == 4) {
         const float* src = (const float*)a.src + ((int64_t)k * a.H + (row_in ? j : 0)) * a.W;
         float* d = (float*)drow;
-        for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x) {
-            const int i = ip - kPadLo;
-            d[ip] = (row_in && i >= 0 && i < a.W) ? src[i] : 0.0f;
+        if ((a.W & 1) == 0 && (reinterpret_cast<uintptr_t>(a.src) & 7) == 0) {
+            // four staged pixels per store (rows start 32-byte aligned); their
+            // sources are two 8-byte aligned pairs (kPadLo = 2), each loaded
+            // whole when it lies on the row
+            float4* d4 = (float4*)d;
+            for (int c = threadIdx.x; c < (a.Wp >> 2); c += blockDim.x) {
+                const int i = 4 * c - kPadLo;
+                float2 lo = make_float2(0.0f, 0.0f), hi = make_float2(0.0f, 0.0f);
+                if (row_in) {   // W even: a pair is wholly on the row or wholly off it
+                    if (i >= 0 && i < a.W) lo = *(const float2*)(src + i);
+                    if (i + 2 < a.W) hi = *(const float2*)(src + i + 2);
+                }
+                d4[c] = make_float4(lo.x, lo.y, hi.x, hi.y);
+            }
+        } else {
+            for (int ip = threadIdx.x; ip < a.Wp; ip += blockDim.x) {
+                const int i = ip - kPadLo;
+                d[ip] = (row_in && i >= 0 && i < a.W) ? src[i] : 0.0f;
+            }
         }
     } else {
         const unsigned short* src =
