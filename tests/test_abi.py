@@ -338,3 +338,26 @@ def test_normalize_matrices(fdk):
     bad[0, 0, 0] = float("nan")
     with pytest.raises(fdk.FdkError):
         fdk.normalize_matrices(bad)
+
+
+def test_empty_and_limit_arguments(fdk):
+    """Empty stacks, grids past the size limit and invalid slab sizes are
+    rejected on the host."""
+    import numpy as np
+    lib = fdk.load()
+    mats, W, H = _case()
+    v = fdk.Volume(16, 1.0).c()
+    empty = fdk.Geometry(np.zeros((0, 3, 4)), W, H)
+    with pytest.raises(fdk.FdkError) as ei:
+        fdk.validate(empty, fdk.Volume(16, 1.0))
+    assert ei.value.status == -1
+    with pytest.raises(fdk.FdkError) as ei:
+        fdk.validate(fdk.Geometry(mats, W, H), fdk.Volume(32769, 1.0, z_count=1))
+    assert ei.value.status == -1
+    p = fdk.Geometry(mats, W, H).c(1, fdk.F32)
+    for slab in (0, -3):
+        assert lib.fdk_backproject_streamed(ctypes.byref(v), ctypes.byref(p), 1, slab, 0, 0, None) == -1
+    assert lib.fdk_backproject_streamed(ctypes.byref(v), ctypes.byref(p), 1, 4, 2, 0, None) == -1   # flags
+    assert lib.fdk_backproject_streamed(ctypes.byref(v), ctypes.byref(p), None, 4, 0, 0, None) == -1
+    n = ctypes.c_int32()
+    assert lib.fdk_streamed_plan(ctypes.byref(v), ctypes.byref(p), 0, ctypes.byref(n), None, None) == -1
