@@ -29,7 +29,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOP_PER_UPDATE = 23          # algorithmic FP operations of one voxel update
+FLOP_PER_UPDATE = 23          # FP operations of one voxel update: coordinates, reciprocal, bilinear, weight
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_FP32_NONPACKED = 78.6    # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, without packed FP32
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "bp_f32_512x496_counters.json")

@@ -66,7 +66,7 @@ def load():
         return _lib
     if not os.path.exists(_build.LIB):
         raise FdkError(-3, f"HIP library not built: {_build.LIB} is missing "
-                           "(run __graft_entry__.build())")
+                           "(build it with: python -m paper_1401_3615_amd._build)")
     lib = ctypes.CDLL(_build.LIB)
     vp, i32 = ctypes.c_void_p, ctypes.c_int32
     pv, pp, ps = ctypes.POINTER(_Volume), ctypes.POINTER(_Proj), ctypes.POINTER(_Scan)
