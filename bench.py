@@ -230,6 +230,12 @@ def main() -> int:
         m = time_steps(fn, max(1, min(args.steps, 3)), 1, stream)
         extra["adjoint_gups"] = updates / (m * 1e-3) / 1e9
         extra["adjoint_ms_per_step"] = m
+        sup = supported_gups(updates, m)
+        if sup is not None:
+            # four FP64 LDS atomic adds per supported update (a lower bound: samples near a
+            # tile edge are scattered by both tiles)
+            extra["adjoint_supported_gups"] = sup
+            extra["adjoint_lds_atomics_per_s"] = 4.0 * sup * 1e9
         log(f"adjoint 512^3x496: {m:.2f} ms/step, {extra['adjoint_gups']:.1f} GUp/s")
         del pout
 
