@@ -789,7 +789,7 @@ fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const 
 
 namespace {
 
-constexpr int kMaxFilterWidth = 2048;   // FFT size 4096: 2.25 x 4096 FP64 complex = 144 KiB of LDS
+constexpr int kMaxFilterWidth = 2048;   // FFT size 4096: 1.25 x 4096 FP64 complex = 80 KiB of LDS
 constexpr size_t kFilterCacheMax = 2;
 
 double ramp_tap(int64_t n, double tau)
@@ -863,6 +863,33 @@ std::string filter_key(const fdk_filter_geometry* g)
 
 // Tables of one geometry: kernel spectrum (gain / M folded in), twiddles,
 // cosine weights (H x W) and short-scan weights (N x W), all from FP64.
+// Frequency held at each position after the in-place decimation-in-frequency
+// FFT of length M (a radix-2 stage first when log2 M is odd, then radix-4):
+// a stage of radix r over blocks of n leaves sub-spectrum d (frequencies
+// d + r k) in the d-th block of n / r, so p = d (n / r) + p' holds
+// d + r f'(p').
+std::vector<int> dif_order(int M)
+{
+    std::vector<int> radix;
+    int lg = 0;
+    while ((1 << lg) < M) ++lg;
+    if (lg & 1) radix.push_back(2);
+    for (int i = 0; i < lg / 2; ++i) radix.push_back(4);
+    std::vector<int> order(M);
+    for (int p = 0; p < M; ++p) {
+        int n = M, rest = p, f = 0, mult = 1;
+        for (int r : radix) {
+            const int sub = n / r, d = rest / sub;
+            f += d * mult;
+            mult *= r;
+            rest -= d * sub;
+            n = sub;
+        }
+        order[p] = f;
+    }
+    return order;
+}
+
 fdk_status filter_tables(DeviceState& d, const fdk_filter_geometry* g, hipStream_t s, FilterEntry** out)
 {
     std::string key = filter_key(g);
@@ -882,10 +909,14 @@ fdk_status filter_tables(DeviceState& d, const fdk_filter_geometry* g, hipStream
     for (int t = 0; t < M; ++t) cosv[t] = std::cos(2.0 * M_PI * (double)t / (double)M);
     std::vector<double> hs(M), wc((size_t)H * W), wp((size_t)N * W);
     std::vector<double> tw((size_t)M / 2);   // M/4 complex
-    for (int m = 0; m < M; ++m) {
+    // the kernel works on the spectrum in the order its in-place decimation-
+    // in-frequency FFT leaves it: position p holds frequency dif_order(p)
+    const std::vector<int> order = dif_order(M);
+    for (int p = 0; p < M; ++p) {
+        const int m = order[p];
         double acc = ramp_tap(0, tau);
         for (int n = 1; n < W; n += 2) acc += 2.0 * ramp_tap(n, tau) * cosv[(int)(((int64_t)m * n) % M)];
-        hs[m] = acc * gain;
+        hs[p] = acc * gain;
     }
     for (int t = 0; t < M / 4; ++t) {
         tw[2 * t] = cosv[t];

@@ -7,11 +7,16 @@
 // imaginary parts of one complex sequence: the ramp kernel is real and even,
 // so its spectrum is real and multiplying the packed spectrum by it filters
 // both rows independently.  The linear convolution is a circular one of
-// length M >= 2W - 1 (rows zero-padded), computed as FFT, multiply, inverse
-// FFT (the inverse through conjugation: conj(FFT(conj(Z H)))), with radix-4
-// Stockham passes in LDS (ping-pong buffers, no bit reversal).  The weights,
-// the kernel spectrum (with the output gain and 1/M folded in) and the
-// twiddles come from FP64 tables computed on the host.
+// length M >= 2W - 1 (rows zero-padded), computed in place in one LDS buffer:
+// a decimation-in-frequency FFT (a radix-2 stage first when log2 M is odd,
+// then radix-4 stages) leaves the spectrum in digit-reversed order, the
+// kernel spectrum is multiplied in that order (the host stores it permuted),
+// and the inverse runs the same stages in reverse order, each twiddling its
+// inputs before the butterfly, on the conjugated data (the inverse of the
+// stage product, up to 1/M and conjugation).  One buffer of M complex values
+// plus the twiddles is 80 KiB at M = 4096, so two workgroups share a CU.  The
+// weights, the permuted kernel spectrum (with the output gain and 1/M folded
+// in) and the twiddles come from FP64 tables computed on the host.
 //
 // The arithmetic is FP64 (full rate on gfx950's vector units) and only the
 // output is rounded to FP32: the ramp filter amplifies white rounding noise
@@ -32,73 +37,107 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Forward DFT (length M, power of two >= 4) of buf0 by Stockham passes in
-// LDS: radix-4 while four sub-transforms fit, then one radix-2 pass if
-// log2(M) is odd.  tw holds exp(-2 pi i t / M) for t < M/4; the powers w^2,
-// w^3 are formed by multiplication and the radix-2 twiddles beyond M/4 by a
-// quarter turn.  Returns the buffer that holds the result.
-__device__ __forceinline__ double2* fft(double2* buf0, double2* buf1, const double2* tw, int M)
+// exp(-2 pi i t / M) for t < M / 2 from the quarter table (beyond M / 4 by a
+// quarter turn)
+__device__ __forceinline__ double2 twiddle_half(const double2* tw, int t, int q)
 {
-    double2* in = buf0;
-    double2* out = buf1;
+    if (t < q) return tw[t];
+    const double2 r = tw[t - q];
+    return make_double2(r.y, -r.x);
+}
+
+// Radix-4 butterfly of the legs in place: y_r = sum_m x_m (-i)^(r m).
+__device__ __forceinline__ void dft4(double2& x0, double2& x1, double2& x2, double2& x3)
+{
+    const double2 a = make_double2(x0.x + x2.x, x0.y + x2.y), b = make_double2(x0.x - x2.x, x0.y - x2.y);
+    const double2 c = make_double2(x1.x + x3.x, x1.y + x3.y);
+    const double2 d = make_double2(x1.y - x3.y, x3.x - x1.x);   // -i (x1 - x3)
+    x0 = make_double2(a.x + c.x, a.y + c.y);
+    x1 = make_double2(b.x + d.x, b.y + d.y);
+    x2 = make_double2(a.x - c.x, a.y - c.y);
+    x3 = make_double2(b.x - d.x, b.y - d.y);
+}
+
+// Decimation-in-frequency stages over blocks of Bs = M, M/r1, ...: radix-2
+// (when log2 M is odd) then radix-4; a stage's outputs are multiplied by
+// exp(-2 pi i r i / Bs) (leg r, index i in the block's first quarter/half).
+__device__ __forceinline__ void dif(double2* x, const double2* tw, int M, bool odd)
+{
     const int q = M >> 2;
-    int Ns = 1;
-    for (; 4 * Ns <= M; Ns <<= 2) {
-        const int tstep = q / Ns;
-        for (int j = threadIdx.x; j < q; j += kFilterThreads) {
-            const int k = j & (Ns - 1);
-            const double2 w = tw[k * tstep];
-            const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
-            const double2 v0 = in[j];
-            const double2 v1 = cmul(in[j + q], w);
-            const double2 v2 = cmul(in[j + 2 * q], w2);
-            const double2 v3 = cmul(in[j + 3 * q], w3);
-            const double2 a0 = make_double2(v0.x + v2.x, v0.y + v2.y), a1 = make_double2(v0.x - v2.x, v0.y - v2.y);
-            const double2 a2 = make_double2(v1.x + v3.x, v1.y + v3.y);
-            const double2 a3 = make_double2(v1.y - v3.y, v3.x - v1.x);   // -i (v1 - v3)
-            const int o = ((j - k) << 2) + k;
-            out[o] = make_double2(a0.x + a2.x, a0.y + a2.y);
-            out[o + Ns] = make_double2(a1.x + a3.x, a1.y + a3.y);
-            out[o + 2 * Ns] = make_double2(a0.x - a2.x, a0.y - a2.y);
-            out[o + 3 * Ns] = make_double2(a1.x - a3.x, a1.y - a3.y);
-        }
-        __syncthreads();
-        double2* t = in;
-        in = out;
-        out = t;
-    }
-    if (Ns < M) {   // Ns = M / 2: radix-2 pass, twiddle exp(-2 pi i j / M)
+    int Bs = M;
+    if (odd) {
         const int h = M >> 1;
         for (int j = threadIdx.x; j < h; j += kFilterThreads) {
-            double2 w;
-            if (j < q) {
-                w = tw[j];
-            } else {
-                const double2 r = tw[j - q];
-                w = make_double2(r.y, -r.x);
-            }
-            const double2 v0 = in[j];
-            const double2 v1 = cmul(in[j + h], w);
-            out[j] = make_double2(v0.x + v1.x, v0.y + v1.y);
-            out[j + h] = make_double2(v0.x - v1.x, v0.y - v1.y);
+            const double2 a = x[j], b = x[j + h];
+            x[j] = make_double2(a.x + b.x, a.y + b.y);
+            x[j + h] = cmul(make_double2(a.x - b.x, a.y - b.y), twiddle_half(tw, j, q));
         }
         __syncthreads();
-        in = out;
+        Bs = h;
     }
-    return in;
+    for (; Bs >= 4; Bs >>= 2) {
+        const int L = Bs >> 2, s = M / Bs;
+        for (int t = threadIdx.x; t < q; t += kFilterThreads) {
+            const int i = t & (L - 1), b0 = (t - i) << 2;
+            double2* p = x + b0 + i;
+            double2 x0 = p[0], x1 = p[L], x2 = p[2 * L], x3 = p[3 * L];
+            dft4(x0, x1, x2, x3);
+            const double2 w = tw[i * s];
+            const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
+            p[0] = x0;
+            p[L] = cmul(x1, w);
+            p[2 * L] = cmul(x2, w2);
+            p[3 * L] = cmul(x3, w3);
+        }
+        __syncthreads();
+    }
+}
+
+// The inverse of the dif() stage product up to a factor M, on conjugated
+// data: the stages in reverse order, each multiplying its legs by the same
+// twiddles first and then applying the butterfly.
+__device__ __forceinline__ void dif_reverse(double2* x, const double2* tw, int M, bool odd)
+{
+    const int q = M >> 2;
+    const int top = odd ? (M >> 1) : M;   // block size of the first radix-4 stage of dif()
+    for (int Bs = 4; Bs <= top; Bs <<= 2) {
+        const int L = Bs >> 2, s = M / Bs;
+        for (int t = threadIdx.x; t < q; t += kFilterThreads) {
+            const int i = t & (L - 1), b0 = (t - i) << 2;
+            double2* p = x + b0 + i;
+            const double2 w = tw[i * s];
+            const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
+            double2 x0 = p[0], x1 = cmul(p[L], w), x2 = cmul(p[2 * L], w2), x3 = cmul(p[3 * L], w3);
+            dft4(x0, x1, x2, x3);
+            p[0] = x0;
+            p[L] = x1;
+            p[2 * L] = x2;
+            p[3 * L] = x3;
+        }
+        __syncthreads();
+    }
+    if (odd) {
+        const int h = M >> 1;
+        for (int j = threadIdx.x; j < h; j += kFilterThreads) {
+            const double2 a = x[j], b = cmul(x[j + h], twiddle_half(tw, j, q));
+            x[j] = make_double2(a.x + b.x, a.y + b.y);
+            x[j + h] = make_double2(a.x - b.x, a.y - b.y);
+        }
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(kFilterThreads) void filter_kernel(FilterArgs f)
 {
-    extern __shared__ double2 lds2[];   // 2 M complex buffers + M/4 twiddles
+    extern __shared__ double2 lds2[];   // M complex values + M/4 twiddles
     const int pairs = (f.H + 1) >> 1;
     const int k = (int)(blockIdx.x / pairs);
     const int j0 = 2 * (int)(blockIdx.x - k * pairs), j1 = j0 + 1;
     const bool has1 = j1 < f.H;
     const int M = f.M;
-    double2* b0 = lds2;
-    double2* b1 = lds2 + M;
-    double2* tws = lds2 + 2 * M;
+    const bool odd = (__builtin_ctz(M) & 1) != 0;
+    double2* x = lds2;
+    double2* tws = lds2 + M;
     for (int t = threadIdx.x; t < (M >> 2); t += kFilterThreads) tws[t] = f.tw[t];
     const float* s0 = f.src + ((int64_t)k * f.H + j0) * f.W;
     const float* s1 = s0 + f.W;
@@ -112,23 +151,23 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(FilterArgs f)
             x0 = (double)s0[i] * c0[i] * w;
             if (has1) x1 = (double)s1[i] * c1[i] * w;
         }
-        b0[i] = make_double2(x0, x1);
+        x[i] = make_double2(x0, x1);
     }
     __syncthreads();
-    double2* z = fft(b0, b1, tws, M);
-    // conj(Z H): H real (kernel even), gain / M folded in
+    dif(x, tws, M, odd);
+    // conj(Z H) in the digit-reversed order of the spectrum (hs is stored so)
     for (int m = threadIdx.x; m < M; m += kFilterThreads) {
         const double h = f.hs[m];
-        const double2 v = z[m];
-        z[m] = make_double2(v.x * h, -v.y * h);
+        const double2 v = x[m];
+        x[m] = make_double2(v.x * h, -v.y * h);
     }
     __syncthreads();
-    double2* y = fft(z, z == b0 ? b1 : b0, tws, M);
-    // inverse = conj of the forward transform of the conjugate
+    dif_reverse(x, tws, M, odd);
+    // the conjugate of the result: row 0 real part, row 1 minus imaginary part
     float* d0 = f.dst + ((int64_t)k * f.H + j0) * f.W;
     float* d1 = d0 + f.W;
     for (int i = threadIdx.x; i < f.W; i += kFilterThreads) {
-        const double2 v = y[i];
+        const double2 v = x[i];
         d0[i] = (float)v.x;
         if (has1) d1[i] = (float)-v.y;
     }
@@ -139,7 +178,7 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(FilterArgs f)
 hipError_t launch_filter(const FilterArgs& f, hipStream_t s)
 {
     const int64_t blocks = (int64_t)f.n_proj * ((f.H + 1) / 2);
-    const size_t lds = (size_t)(2 * f.M + f.M / 4) * sizeof(double2);
+    const size_t lds = (size_t)(f.M + f.M / 4) * sizeof(double2);
     if (blocks < 1 || blocks > 0x7fffffffLL || f.M < 4 || (f.M & (f.M - 1)) != 0 || lds > 160 * 1024)
         return hipErrorInvalidValue;
     static bool attr_set = false;

@@ -80,9 +80,10 @@ struct FilterArgs {
     float* dst;                  // n_proj x H x W filtered (FP32)
     const double* wc;            // H x W cosine weights
     const double* wp;            // n_proj x W short-scan weights
-    const double* hs;            // M: real spectrum of the circular ramp kernel x gain / M
+    const double* hs;            // M: real spectrum of the circular ramp kernel x gain / M, in the
+                                 // order the in-place FFT leaves the spectrum
     const double2* tw;           // M / 4 twiddles exp(-2 pi i t / M)
-    int32_t n_proj, W, H, M;     // M: power of two >= 2 W - 1, 2.25 M FP64 complex fit 160 KiB of LDS
+    int32_t n_proj, W, H, M;     // M: power of two >= 2 W - 1, 1.25 M FP64 complex fit 80 KiB of LDS
 };
 hipError_t launch_filter(const FilterArgs& f, hipStream_t s);
 
