@@ -260,7 +260,8 @@ fdk_status fdk_streamed_plan(const fdk_volume* vol, const fdk_projections* proj,
  *   volume     DEVICE, z_count * L * L float32: the start x0 when requested,
  *              else overwritten; the result x_n on return
  *   n_iter     >= 0 iterations
- *   history    DEVICE doubles or NULL (see each solver)
+ *   history    DEVICE doubles or NULL (see each solver); FDK_E_INVALID_ARG if
+ *              it is not device memory
  * The library holds four solver vectors (two of the projection stack's size,
  * two of the volume's) until fdk_release_workspace.  Buffers must not
  * overlap.  Errors as for the projectors; on a validation error nothing is

@@ -1032,13 +1032,20 @@ struct IterSetup {
 };
 
 fdk_status iter_setup(const fdk_volume* vol, const fdk_projections* proj, float* volume, int32_t n_iter,
-                      void* stream, IterSetup& it)
+                      const double* history, void* stream, IterSetup& it)
 {
     fdk_status st = fdk_validate(vol, proj, 1);
     if (st != FDK_OK) return st;
     if (proj->dtype != FDK_F32) return fail(FDK_E_UNSUPPORTED, "iterative solvers take FP32 projections");
     if (volume == nullptr) return fail(FDK_E_INVALID_ARG, "volume buffer is NULL");
     if (n_iter < 0) return fail(FDK_E_INVALID_ARG, "n_iter=%d < 0", n_iter);
+    if (history != nullptr) {   // written by a kernel: it must be device (or managed) memory
+        hipPointerAttribute_t attr{};
+        const bool ok = hipPointerGetAttributes(&attr, history) == hipSuccess &&
+                        (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged);
+        (void)hipGetLastError();
+        if (!ok) return fail(FDK_E_INVALID_ARG, "history is not device memory");
+    }
     if ((st = device_state(&it.d)) != FDK_OK) return st;
     it.s = static_cast<hipStream_t>(stream);
     it.nv = (int64_t)vol->z_count * vol->L * vol->L;
@@ -1081,7 +1088,7 @@ fdk_status fdk_cgls(const fdk_volume* vol, const fdk_projections* proj, float* v
     std::lock_guard<std::recursive_mutex> lock(g_mu);
     load_env_tuning();
     IterSetup it;
-    fdk_status st = iter_setup(vol, proj, volume, n_iter, stream, it);
+    fdk_status st = iter_setup(vol, proj, volume, n_iter, history, stream, it);
     if (st != FDK_OK) return st;
     const float* p = static_cast<const float*>(proj->data);
     float *r = it.p0, *q = it.p1, *sv = it.v0, *dv = it.v1;
@@ -1133,7 +1140,7 @@ fdk_status fdk_sirt(const fdk_volume* vol, const fdk_projections* proj, float* v
         return fail(FDK_E_INVALID_ARG, "lambda must be finite and > 0");
     if (flags & ~(FDK_SIRT_USE_X0 | FDK_SIRT_NONNEG)) return fail(FDK_E_INVALID_ARG, "unknown flags 0x%x", flags);
     IterSetup it;
-    fdk_status st = iter_setup(vol, proj, volume, n_iter, stream, it);
+    fdk_status st = iter_setup(vol, proj, volume, n_iter, history, stream, it);
     if (st != FDK_OK) return st;
     const float* p = static_cast<const float*>(proj->data);
     float *r = it.p0, *rw = it.p1, *t = it.v0, *cw = it.v1;

@@ -361,3 +361,15 @@ def test_empty_and_limit_arguments(fdk):
     assert lib.fdk_backproject_streamed(ctypes.byref(v), ctypes.byref(p), None, 4, 0, 0, None) == -1
     n = ctypes.c_int32()
     assert lib.fdk_streamed_plan(ctypes.byref(v), ctypes.byref(p), 0, ctypes.byref(n), None, None) == -1
+
+
+def test_solver_history_must_be_device_memory(fdk):
+    import numpy as np
+    lib = fdk.load()
+    mats, W, H = _case()
+    v = fdk.Volume(16, 1.0).c()
+    p = fdk.Geometry(mats, W, H).c(1, fdk.F32)
+    host = np.zeros(4)
+    assert lib.fdk_cgls(ctypes.byref(v), ctypes.byref(p), 1, 2, 0, host.ctypes.data, None) == -1
+    assert b"history" in lib.fdk_last_error()
+    assert lib.fdk_sirt(ctypes.byref(v), ctypes.byref(p), 1, 2, 1.0, 0, host.ctypes.data, None) == -1
