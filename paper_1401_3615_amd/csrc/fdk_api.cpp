@@ -532,6 +532,7 @@ TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, Til
     a.win = nullptr;
     a.rot_div = 0;
     a.const_w = 0;
+    a.raw = 0;
     return a;
 }
 
@@ -1472,13 +1473,16 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
     for (int i = 0; i < n_scans; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return scans[a].proj.n_proj > scans[b].proj.n_proj; });
+    // FP32 scans that sample from LDS read their windows straight from the
+    // caller's images (bounds-checked loads); the others are staged
+    auto is_raw = [&](const fdk_projections* p) { return p->dtype == FDK_F32 && scan_layout(p) == 3; };
     uint64_t stage_total = 0;
     std::vector<uint64_t> stage_off(n_scans);
     for (int j = 0; j < n_scans; ++j) {
         const int i = order[j];
         stage_off[j] = stage_total;
         const int es_i = esize_of(scans[i].proj.dtype);
-        stage_total += staged_bytes(&scans[i].proj, es_i, scan_layout(&scans[i].proj));
+        if (!is_raw(&scans[i].proj)) stage_total += staged_bytes(&scans[i].proj, es_i, scan_layout(&scans[i].proj));
     }
 
     if ((st = begin_call(*d, s)) != FDK_OK) return st;
@@ -1516,7 +1520,8 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         std::vector<const float*> scale_ptrs;
         scale_ptrs.reserve(total_proj);
         std::vector<TileArgs> tiles(n_scans);
-        std::vector<StageArgs> stages(n_scans);
+        std::vector<StageArgs> stages;
+        stages.reserve(n_scans);
         std::vector<int32_t> item_begin(n_scans + 1);
         std::vector<float> out_scales(n_scans);
         std::vector<int> proj_begin(n_scans);
@@ -1538,8 +1543,11 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
             const int es = esize_of(sc.proj.dtype);
             TileShape ts = t;
             ts.layout = scan_layout(&sc.proj);
-            stages[j] = make_stage(&sc.proj, es, ts.layout, static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j], rows);
-            rows += (int64_t)sc.proj.n_proj * stages[j].Hp;
+            if (!is_raw(&sc.proj)) {
+                stages.push_back(make_stage(&sc.proj, es, ts.layout,
+                                            static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j], rows));
+                rows += (int64_t)sc.proj.n_proj * stages.back().Hp;
+            }
             item_begin[j] = (int32_t)items;
             TileArgs probe = make_args(&sc.vol, &sc.proj, es, ts, nullptr, nullptr, nullptr, 1.0f, 0, sc.proj.dtype);
             const int64_t n_tiles = (int64_t)probe.tiles_x * probe.tiles_y * probe.tiles_z;
@@ -1557,7 +1565,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         auto alloc = [&](DevBuf& buf, size_t n) { if (e == hipSuccess) e = ensure(buf, n); };
         alloc(b.tiles, n_scans * sizeof(TileArgs));
         alloc(b.item_begin, (n_scans + 1) * sizeof(int32_t));
-        alloc(b.stage, n_scans * sizeof(StageArgs));
+        alloc(b.stage, std::max<size_t>(1, stages.size()) * sizeof(StageArgs));
         alloc(b.scale_ptrs, (size_t)total_proj * sizeof(float*));
         alloc(b.coef64, coef64.size() * sizeof(double));
         alloc(b.coef_dev, (size_t)total_proj * 16 * sizeof(double));
@@ -1576,13 +1584,21 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
                                  static_cast<double*>(b.coef_dev.p) + (size_t)proj_begin[j] * 16, sc.volume,
                                  out_scales[j], accumulate, sc.proj.dtype);
             if (win_off[j] >= 0) tiles[j].win = static_cast<const Win*>(b.windows.p) + win_off[j];
+            if (is_raw(&sc.proj)) {   // the caller's unpadded images, row pitch W
+                const uint64_t img = (uint64_t)sc.proj.width * sc.proj.height * 4;
+                tiles[j].proj = static_cast<const unsigned char*>(sc.proj.data);
+                tiles[j].proj_stride = img;
+                tiles[j].proj_bytes = (uint32_t)img;
+                tiles[j].row_bytes = (uint32_t)sc.proj.width * 4;
+                tiles[j].raw = 1;
+            }
         }
         auto up = [&](DevBuf& buf, const void* src, size_t n) {
             if (e == hipSuccess) e = hipMemcpyAsync(buf.p, src, n, hipMemcpyHostToDevice, s);
         };
         up(b.tiles, tiles.data(), tiles.size() * sizeof(TileArgs));
         up(b.item_begin, item_begin.data(), item_begin.size() * sizeof(int32_t));
-        up(b.stage, stages.data(), stages.size() * sizeof(StageArgs));
+        if (!stages.empty()) up(b.stage, stages.data(), stages.size() * sizeof(StageArgs));
         up(b.scale_ptrs, scale_ptrs.data(), scale_ptrs.size() * sizeof(float*));
         up(b.coef64, coef64.data(), coef64.size() * sizeof(double));
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1595,7 +1611,8 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         if ((int64_t)grid > items) grid = (int)items;
         if (e == hipSuccess) e = hipStreamBeginCapture(d->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t e1 = launch_stage_batched(static_cast<const StageArgs*>(b.stage.p), n_scans, rows, d->capture_stream);
+            hipError_t e1 = launch_stage_batched(static_cast<const StageArgs*>(b.stage.p), (int)stages.size(), rows,
+                                                 d->capture_stream);
             hipError_t e2 = launch_fold(static_cast<const double*>(b.coef64.p),
                                         static_cast<const float* const*>(b.scale_ptrs.p),
                                         static_cast<double*>(b.coef_dev.p), total_proj, d->capture_stream);

@@ -630,9 +630,41 @@ struct Fill {
     int lo[kPre];   // LDS float offset of chunk i of this thread, -1 if it has none
 };
 
-template <typename T, int NW>
-__device__ __forceinline__ void window_prefetch(Fill& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs, int wp)
+// Unpadded source images (RAW): window pixel (ip, jp) is image pixel
+// (ip - kPadLo, jp - kPadLo); a window that reaches past the image (edge) has
+// the chunk elements off the image zeroed after the load (the loads are
+// range-checked buffer loads, so an address off the image cannot fault).
+struct RawImg {
+    int W, H;
+};
+
+__device__ __forceinline__ bool raw_edge(const LdsWin& w, const RawImg& im)
 {
+    return w.c_lo < kPadLo || w.c_hi - kPadLo >= im.W || w.j0 < kPadLo || w.j1 - kPadLo >= im.H;
+}
+
+template <typename T, bool RAWOK>
+__device__ __forceinline__ float4 window_chunk(__amdgpu_buffer_rsrc_t rs, const LdsWin& w, int wp, int r, int cc,
+                                               const RawImg& im, bool raw, bool edge)
+{
+    if (!RAWOK || !raw) return Chunk<T>::load(rs, (uint32_t)(__mul24(w.j0 + r, wp) + w.c_lo + 4 * cc));
+    const int j = w.j0 + r - kPadLo, i = w.c_lo - kPadLo + 4 * cc;
+    float4 v = Chunk<T>::load(rs, (uint32_t)(j * wp + i));
+    if (edge) {
+        const bool row = (unsigned)j < (unsigned)im.H;
+        v.x = row && (unsigned)i < (unsigned)im.W ? v.x : 0.0f;
+        v.y = row && (unsigned)(i + 1) < (unsigned)im.W ? v.y : 0.0f;
+        v.z = row && (unsigned)(i + 2) < (unsigned)im.W ? v.z : 0.0f;
+        v.w = row && (unsigned)(i + 3) < (unsigned)im.W ? v.w : 0.0f;
+    }
+    return v;
+}
+
+template <typename T, int NW, bool RAWOK = false>
+__device__ __forceinline__ void window_prefetch(Fill& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs, int wp,
+                                                const RawImg& im = RawImg{0, 0}, bool raw = false)
+{
+    const bool edge = RAWOK && raw && raw_edge(w, im);
     // chunk e = t + i * NT of the window, row-major by 4-pixel chunks: row and
     // column are found once and then stepped by NT
     // (e + 0.5) * rcp(nc) floors to e / nc exactly: the relative error of the
@@ -647,7 +679,7 @@ __device__ __forceinline__ void window_prefetch(Fill& f, const LdsWin& w, __amdg
     for (int i = 0; i < kPre; ++i) {
         f.lo[i] = -1;
         if (e < w.total) {
-            f.v[i] = Chunk<T>::load(rs, (uint32_t)(__mul24(w.j0 + r, wp) + w.c_lo + 4 * cc));
+            f.v[i] = window_chunk<T, RAWOK>(rs, w, wp, r, cc, im, raw, edge);
             f.lo[i] = __mul24(r, w.tw) + 4 * cc;
         }
         e += NT;
@@ -660,19 +692,20 @@ __device__ __forceinline__ void window_prefetch(Fill& f, const LdsWin& w, __amdg
     }
 }
 
-template <typename T, int NW>
+template <typename T, int NW, bool RAWOK = false>
 __device__ __forceinline__ void window_store(float* lds, const Fill& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs,
-                                             int wp)
+                                             int wp, const RawImg& im = RawImg{0, 0}, bool raw = false)
 {
 #pragma unroll
     for (int i = 0; i < kPre; ++i)
         if (f.lo[i] >= 0) *reinterpret_cast<float4*>(&lds[f.lo[i]]) = f.v[i];
+    const bool edge = RAWOK && raw && raw_edge(w, im);
     const float inv_nc = __builtin_amdgcn_rcpf((float)w.nc);
     for (int e = (int)threadIdx.x + kPre * kWave * NW; e < w.total; e += kWave * NW) {
         const int r = (int)(((float)e + 0.5f) * inv_nc);
         const int cc = e - __mul24(r, w.nc);
         *reinterpret_cast<float4*>(&lds[__mul24(r, w.tw) + 4 * cc]) =
-            Chunk<T>::load(rs, (uint32_t)(__mul24(w.j0 + r, wp) + w.c_lo + 4 * cc));
+            window_chunk<T, RAWOK>(rs, w, wp, r, cc, im, raw, edge);
     }
 }
 
@@ -680,10 +713,37 @@ __device__ __forceinline__ void window_store(float* lds, const Fill& f, const Ld
 // CWM: 1 every projection has w constant along z (one 1/w per strip), 0 none
 // is assumed to, 2 decided per projection (the persistent kernel, whose scans
 // differ).
-template <typename T, int S, int NW, int CWM>
+// Bilinear sample of an unpadded FP32 image at (anchor + (dx, dy)), zero off
+// the detector; out of line (see the caller).
+__device__ __attribute__((noinline)) float raw_sample(const unsigned char* img, uint32_t bytes, float dx, float dy,
+                                                      int ia, int ja, int W, int H)
+{
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, bytes);
+    const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
+    const int i0 = cvt_floor(dx) + ia, j0 = cvt_floor(dy) + ja;
+    float tap[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = i0 + (q & 1), j = j0 + (q >> 1);
+        const float v =
+            __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(j * W + i) * 4u, 0, 0));
+        tap[q] = (unsigned)i < (unsigned)W && (unsigned)j < (unsigned)H ? v : 0.0f;
+    }
+    const float top = fmaf(sx, tap[1] - tap[0], tap[0]);
+    const float bot = fmaf(sx, tap[3] - tap[2], tap[2]);
+    return fmaf(sy, bot - top, top);
+}
+
+// RAWOK: the launch may hold scans whose images are unpadded (a.raw); their
+// windows are filled with bounds checks and their oversized windows gathered
+// with per-tap checks.
+template <typename T, int S, int NW, int CWM, bool RAWOK = false>
 __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot_div, float* lds)
 {
     const TilePos p = tile_pos<S, NW>(a, tile);
+    const bool raw = RAWOK && a.raw != 0;
+    // image size from the clamp range of the centred coordinates (hi = size + 1 - centre)
+    const RawImg im{(int)a.hi_x + a.cu - 1, (int)a.hi_y + a.cv - 1};
     float acc[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[s] = 0.0f;
@@ -696,7 +756,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     Fill pre;
     LdsWin wv(wins[po.k]);
     bool big = false;
-    if (wv.fits) window_prefetch<T, NW>(pre, wv, make_rsrc(po.img, a.proj_bytes), wp);
+    if (wv.fits) window_prefetch<T, NW, RAWOK>(pre, wv, make_rsrc(po.img, a.proj_bytes), wp, im, raw);
     for (int n = 0; n < a.n_proj; ++n) {
         const Coef cur = load_coef(a.coef, po.k);
         const unsigned char* img = po.img;
@@ -707,10 +767,10 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
         const __amdgpu_buffer_rsrc_t rs_next = make_rsrc(po.img, a.proj_bytes);
         if (wv.fits) {
             __syncthreads();                                // previous projection's reads are done
-            window_store<T, NW>(lds, pre, wv, rs, wp);
+            window_store<T, NW, RAWOK>(lds, pre, wv, rs, wp, im, raw);
             __syncthreads();
         }
-        if (wn.fits) window_prefetch<T, NW>(pre, wn, rs_next, wp);
+        if (wn.fits) window_prefetch<T, NW, RAWOK>(pre, wn, rs_next, wp, im, raw);
         if (wv.fits) {
             const Strip st = strip_setup<2>(cur.c, p, a, wp);
             // anchor in staged-pixel coordinates; clamp so both tap columns
@@ -756,6 +816,25 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
             const Coef cur = load_coef(a.coef, k);
             const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.proj + (uint64_t)k * a.proj_stride, a.proj_bytes);
             const Strip st = strip_setup<Sampler<T, 0>::kShift>(cur.c, p, a, wp);
+            if (RAWOK && raw) {
+                // unpadded image: every tap checked against the detector (an
+                // out-of-line call per sample keeps this rare path's loads out of
+                // the registers of the main loop)
+                const unsigned char* img = a.proj + (uint64_t)k * a.proj_stride;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    constexpr int kMid = S / 2;
+                    const float t = (float)(s - kMid);
+                    const float w = fmaf(t, st.dw, st.wb);
+                    const float r = __builtin_amdgcn_rcpf(w);
+                    const float dx = __builtin_amdgcn_fmed3f(fmaf(t, st.du, st.ub) * r, st.lox, st.hix);
+                    const float dy = __builtin_amdgcn_fmed3f(fmaf(t, st.dv, st.vb) * r, st.loy, st.hiy);
+                    acc[s] = fmaf(raw_sample(img, a.proj_bytes, dx, dy, (int)st.fau + a.cu, (int)st.fav + a.cv, im.W,
+                                             im.H),
+                                  r * r, acc[s]);
+                }
+                continue;
+            }
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 constexpr int kMid = S / 2;
@@ -824,7 +903,7 @@ __global__ __launch_bounds__(kWave * NW)
         if (a.layout == 3) {
             if (a.dtype == 1) bp_lds_tile<__half, S, NW, 2>(a, tile, (int)gridDim.x, lds);
             else if (a.dtype == 2) bp_lds_tile<bf16_t, S, NW, 2>(a, tile, (int)gridDim.x, lds);
-            else bp_lds_tile<float, S, NW, 2>(a, tile, (int)gridDim.x, lds);
+            else bp_lds_tile<float, S, NW, 2, true>(a, tile, (int)gridDim.x, lds);
         } else {
             bp_tile_any<S, NW>(a, tile, (int)gridDim.x);
         }

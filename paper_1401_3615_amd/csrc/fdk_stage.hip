@@ -283,6 +283,7 @@ hipError_t launch_stage(const StageArgs& a, hipStream_t s)
 
 hipError_t launch_stage_batched(const StageArgs* dev_args, int n_stacks, int64_t total_rows, hipStream_t s)
 {
+    if (n_stacks <= 0 || total_rows <= 0) return hipSuccess;   // nothing to stage
     hipLaunchKernelGGL(stage_batched_kernel,
                        dim3((unsigned)((total_rows + kRowsPerBlock - 1) / kRowsPerBlock)), dim3(256), 0, s,
                        dev_args, n_stacks, total_rows);

@@ -158,3 +158,22 @@ def test_batched_layouts(fdk, layout):
     for sc, (L, voxel, mats, q, qd, scale) in zip(scans, host):
         ref = oracle.backproject(L, voxel, mats, q.numpy())
         assert_parity(sc.out.cpu().numpy(), ref, what=f"batched layout {layout} L={L}")
+
+
+@pytest.mark.parametrize("strip,waves", [(32, 4), (8, 2)])
+def test_batched_unstaged_edges_and_large_windows(fdk, strip, waves):
+    """FP32 scans sampling LDS windows read the caller's images directly:
+    windows at the detector edges (volumes overfilling small detectors, odd
+    width) are bounds-checked, and windows larger than the LDS tile (large
+    voxels on a fine detector) take the checked gather."""
+    specs = [(40, 8.0, 7, 48, 36, 31), (36, 8.0, 5, 256, 192, 32), (33, 6.0, 6, 61, 45, 33)]
+    scans, host = make_scans(fdk, specs, [torch.float32] * len(specs))
+    fdk.set_tile(fdk.TUNE_BATCHED, strip, waves, 3)
+    try:
+        fdk.backproject_batched(scans)
+        torch.cuda.synchronize()
+    finally:
+        fdk.set_tile(fdk.TUNE_BATCHED, 0, 0)
+    for sc, (L, voxel, mats, q, qd, scale) in zip(scans, host):
+        ref = oracle.backproject(L, voxel, mats, q.numpy())
+        assert_parity(sc.out.cpu().numpy(), ref, what=f"unstaged L={L} W={sc.geom.width}")
