@@ -41,15 +41,20 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def bp_kernel_name(fdk, vol, mats) -> str:
+def bp_kernel_name(fdk, vol, geom) -> str:
     """Name of the FP32 backprojection kernel the library launches for `vol`
     (the LDS kernel is instantiated for w constant along z, i.e. a zero
-    z-coefficient in every matrix's third row, or not)."""
+    z-coefficient in every matrix's third row, or not, and for reading
+    staged images or the caller's stack in place, which it does for grids
+    with fewer than one voxel per eight projection pixels)."""
     import numpy as np
     strip, waves, layout = fdk.get_tile(vol, fdk.F32)
     if layout == 3:
-        cw = int(bool(np.all(np.asarray(mats)[:, 2, 2] == 0.0)))
-        return f"bp_lds_kernel<float, {strip}, {waves}, {cw}>"
+        m = np.asarray(geom.mats).reshape(-1, 3, 4)
+        cw = int(bool(np.all(m[:, 2, 2] == 0.0)))
+        pixels = len(m) * geom.width * geom.height
+        in_place = vol.planes * vol.L * vol.L * 8 < pixels and os.environ.get("FDK_STAGE_FP32") != "1"
+        return f"bp_lds_kernel<float, {strip}, {waves}, {cw}, {str(in_place).lower()}>"
     return f"bp_kernel<float, {layout}, {strip}, {waves}>"
 
 
@@ -160,7 +165,7 @@ def main() -> int:
             torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
         print(json.dumps({"metric": "fp32_gups", "value": value, "ms_per_step": ms,
-                          "kernel": bp_kernel_name(fdk, vol, mats), "copy_bytes_each_way": COPY_BYTES}), flush=True)
+                          "kernel": bp_kernel_name(fdk, vol, geom), "copy_bytes_each_way": COPY_BYTES}), flush=True)
         return 0
     vol32 = out.clone()
 
@@ -365,7 +370,7 @@ def main() -> int:
             traffic = cnt["hbm_bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "kernel": bp_kernel_name(fdk, vol, mats), "kernel_ms": round(bp_kernel_ms, 3),
+                "kernel": bp_kernel_name(fdk, vol, geom), "kernel_ms": round(bp_kernel_ms, 3),
                 "flop_per_update": FLOP_PER_UPDATE,
                 "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED, 4)}
 

@@ -324,7 +324,13 @@ fdk_status fdk_get_tile(const fdk_volume* vol, int32_t dtype, int32_t* strip, in
  * rejected (its first line must read "fdk-tuning <FDK_ABI_VERSION> gfx950").
  * Returns the number of entries read or a negative fdk_status.
  * fdk_set_tuning_entry sets one entry; strip = waves = 0 removes it.  The
- * environment variable FDK_TUNING_FILE names a file loaded on first use. */
+ * environment variable FDK_TUNING_FILE names a file loaded on first use.
+ * FP32 stacks sampled through LDS windows (layout 3) are read in place, with
+ * bounds-checked window loads, instead of being staged, by
+ * fdk_backproject_batched and by fdk_backproject when the grid has fewer
+ * than one voxel per eight projection pixels (staging would cost more than
+ * the slightly slower loads); FDK_STAGE_FP32=1 in the environment (read on
+ * first use) stages them in every case. */
 int32_t fdk_load_tuning(const char* path);
 fdk_status fdk_set_tuning_entry(int32_t dtype, int32_t size_class, int32_t strip, int32_t waves,
                                 int32_t layout);

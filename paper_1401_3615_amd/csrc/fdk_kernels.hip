@@ -631,9 +631,8 @@ struct Fill {
 };
 
 // Unpadded source images (RAW): window pixel (ip, jp) is image pixel
-// (ip - kPadLo, jp - kPadLo); a window that reaches past the image (edge) has
-// the chunk elements off the image zeroed after the load (the loads are
-// range-checked buffer loads, so an address off the image cannot fault).
+// (ip - kPadLo, jp - kPadLo); a window that reaches past the image (edge) is
+// loaded pixel by pixel, with the pixels off the image set to zero.
 struct RawImg {
     int W, H;
 };
@@ -649,15 +648,21 @@ __device__ __forceinline__ float4 window_chunk(__amdgpu_buffer_rsrc_t rs, const 
 {
     if (!RAWOK || !raw) return Chunk<T>::load(rs, (uint32_t)(__mul24(w.j0 + r, wp) + w.c_lo + 4 * cc));
     const int j = w.j0 + r - kPadLo, i = w.c_lo - kPadLo + 4 * cc;
-    float4 v = Chunk<T>::load(rs, (uint32_t)(j * wp + i));
-    if (edge) {
-        const bool row = (unsigned)j < (unsigned)im.H;
-        v.x = row && (unsigned)i < (unsigned)im.W ? v.x : 0.0f;
-        v.y = row && (unsigned)(i + 1) < (unsigned)im.W ? v.y : 0.0f;
-        v.z = row && (unsigned)(i + 2) < (unsigned)im.W ? v.z : 0.0f;
-        v.w = row && (unsigned)(i + 3) < (unsigned)im.W ? v.w : 0.0f;
+    if (!edge) return Chunk<T>::load(rs, (uint32_t)(__mul24(j, wp) + i));
+    // a window reaching past the image: each pixel on its own, off-image ones
+    // read as zero (adjacent b32 loads are merged into one multi-dword load,
+    // which the buffer range check drops whole when it starts before the
+    // image, in-image pixels included)
+    const bool row = (unsigned)j < (unsigned)im.H;
+    float v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const bool ok = row && (unsigned)(i + e) < (unsigned)im.W;
+        const uint32_t px = ok ? (uint32_t)(__mul24(j, wp) + i + e) : 0u;
+        const float x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, px * 4u, 0, 0));
+        v[e] = ok ? x : 0.0f;
     }
-    return v;
+    return make_float4(v[0], v[1], v[2], v[3]);
 }
 
 template <typename T, int NW, bool RAWOK = false>
@@ -866,12 +871,12 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     }
 }
 
-template <typename T, int S, int NW, int CWM>
+template <typename T, int S, int NW, int CWM, bool RAWOK = false>
 __global__ __launch_bounds__(kWave * NW)
     __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<S, NW>(), lds_waves_per_eu<S, NW>()))) void bp_lds_kernel(TileArgs a)
 {
     __shared__ __attribute__((aligned(16))) float lds[kLdsCap];
-    bp_lds_tile<T, S, NW, CWM>(a, xcd_remap(blockIdx.x, gridDim.x), a.rot_div, lds);
+    bp_lds_tile<T, S, NW, CWM, RAWOK>(a, xcd_remap(blockIdx.x, gridDim.x), a.rot_div, lds);
 }
 
 // Persistent backprojection over many scans: every workgroup pulls
@@ -1242,6 +1247,9 @@ hipError_t bp_dispatch_t(const TileArgs& a, int nblocks, hipStream_t st)
         else if (a.dtype == 2)
             a.const_w ? launch_rotated(bp_lds_kernel<bf16_t, S, NW, 1>, a, grid, block, st)
                       : launch_rotated(bp_lds_kernel<bf16_t, S, NW, 0>, a, grid, block, st);
+        else if (a.raw)
+            a.const_w ? launch_rotated(bp_lds_kernel<float, S, NW, 1, true>, a, grid, block, st)
+                      : launch_rotated(bp_lds_kernel<float, S, NW, 0, true>, a, grid, block, st);
         else
             a.const_w ? launch_rotated(bp_lds_kernel<float, S, NW, 1>, a, grid, block, st)
                       : launch_rotated(bp_lds_kernel<float, S, NW, 0>, a, grid, block, st);

@@ -226,3 +226,34 @@ def test_non_default_stream(fdk):
     st.synchronize()
     ref = oracle.backproject(L, voxel, mats, q.numpy())
     assert_parity(out.cpu().numpy(), ref, what="stream")
+
+
+@pytest.mark.parametrize("L,voxel,W,H,tilt,noise", [(12, 8.0, 160, 128, 0.0, True), (16, 24.0, 48, 40, 0.0, True),
+                                                    (16, 12.0, 48, 40, 0.0, True), (10, 30.0, 256, 200, 1.0, False),
+                                                    (9, 14.0, 61, 47, 2.0, True)])
+def test_small_grid_reads_stack_in_place(fdk, L, voxel, W, H, tilt, noise):
+    """Grids with fewer than one voxel per eight projection pixels read the
+    FP32 stack in place (no staging): windows inside the detector, volumes
+    overfilling it (edge windows, including the first and last image rows),
+    footprints larger than the LDS tile (large voxels on a fine detector) and
+    an odd width.  White-noise images make any misplaced pixel show; the
+    large-footprint case takes filtered phantom projections instead, since
+    with samples a hundred pixels from the centre the FP32 rounding of the
+    sample position alone moves a white-noise backprojection by about 1e-5
+    (relative), for the staged path as much as for this one."""
+    carm = S.CArm(30, W, H, pixel=384.0 / W, tilt_deg=tilt)
+    assert L ** 3 * 8 < 30 * W * H
+    if noise:
+        mats = S.carm_matrices(carm)
+        proj = S.random_projections(30, H, W, 17)
+    else:
+        mats, q = S.filtered_projections(carm, 17)
+        proj = q.numpy()
+    fdk.set_tile(fdk.F32, 16, 4, 3)
+    try:
+        out = fdk.backproject(torch.from_numpy(proj).to(DEV), fdk.Geometry(mats, W, H), fdk.Volume(L, voxel))
+        torch.cuda.synchronize()
+    finally:
+        fdk.set_tile(fdk.F32, 0, 0)
+    ref = oracle.backproject(L, voxel, mats, proj)
+    assert_parity(out.cpu().numpy(), ref, what=f"in place L={L} W={W}")

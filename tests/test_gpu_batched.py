@@ -166,7 +166,8 @@ def test_batched_unstaged_edges_and_large_windows(fdk, strip, waves):
     windows at the detector edges (volumes overfilling small detectors, odd
     width) are bounds-checked, and windows larger than the LDS tile (large
     voxels on a fine detector) take the checked gather."""
-    specs = [(40, 8.0, 7, 48, 36, 31), (36, 8.0, 5, 256, 192, 32), (33, 6.0, 6, 61, 45, 33)]
+    specs = [(40, 8.0, 7, 48, 36, 31), (36, 8.0, 5, 256, 192, 32), (33, 6.0, 6, 61, 45, 33),
+             (16, 24.0, 9, 48, 40, 34), (16, 12.0, 8, 48, 40, 35)]
     scans, host = make_scans(fdk, specs, [torch.float32] * len(specs))
     fdk.set_tile(fdk.TUNE_BATCHED, strip, waves, 3)
     try:
