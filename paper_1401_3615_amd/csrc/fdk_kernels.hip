@@ -380,10 +380,13 @@ struct Coef {
     double c[12];
 };
 
+// Coefficients of projection k, read through the scalar cache (the table is
+// written before the launch and only read during it).
 __device__ __forceinline__ Coef load_coef(const double* tab, int k)
 {
+    using DC = const __attribute__((address_space(4))) double;
     Coef r;
-    const double* t = tab + 16 * k;
+    DC* t = (DC*)(tab + 16 * k);
 #pragma unroll
     for (int i = 0; i < 12; ++i) r.c[i] = t[i];
     return r;
@@ -600,11 +603,13 @@ constexpr int lds_waves_per_eu()
 }
 
 // The window of one projection as the LDS tile holds it: 4-pixel chunks
-// [c_lo, c_hi] x [j0, j1] of the staged image, row pitch tw pixels.
+// [c_lo, c_hi] x [j0, j1] of the staged image, row pitch tw pixels.  It fits
+// when it holds at most kLdsCap pixels in rows of at most NT chunks (NT =
+// threads of the workgroup, which copy a row's chunks side by side).
 struct LdsWin {
     int c_lo, c_hi, j0, j1, tw, th, nc, total;   // total = chunks = nc * th
     bool empty, fits;
-    __device__ __forceinline__ explicit LdsWin(Win w)
+    __device__ __forceinline__ LdsWin(Win w, int max_nc)
     {
         empty = w.i0 > w.i1;
         c_lo = w.i0 & ~3;
@@ -615,19 +620,22 @@ struct LdsWin {
         th = j1 - j0 + 1;
         nc = tw >> 2;
         total = empty ? 0 : nc * th;
-        fits = !empty && tw * th <= kLdsCap;
+        fits = !empty && tw * th <= kLdsCap && nc <= max_nc;
     }
 };
 
 // Chunks of a window prefetched into registers per thread while the previous
-// projection is sampled (kPre x 256 threads x 4 pixels = 4096 pixels for a
-// 4-wave workgroup), with the LDS offset each one goes to; larger windows
+// projection is sampled (up to kPre x 256 threads x 4 pixels = 4096 pixels for
+// a 4-wave workgroup), with the LDS offset each one goes to; larger windows
 // load their remainder after the barrier.
 constexpr int kPre = 4;
 
 struct Fill {
-    float4 v[kPre];
-    int lo[kPre];   // LDS float offset of chunk i of this thread, -1 if it has none
+    float4 v[kPre];   // chunk i: row r0 + i * R of this thread's chunk column
+    int r0, lo0;      // first row and its LDS float offset (r0 >= th: none)
+    uint32_t px0;     // first chunk's source pixel
+    int R, dlo;       // rows per pass and the LDS step per pass (uniform)
+    uint32_t dpx;     // source step per pass (uniform)
 };
 
 // Unpadded source images (RAW): window pixel (ip, jp) is image pixel
@@ -642,59 +650,60 @@ __device__ __forceinline__ bool raw_edge(const LdsWin& w, const RawImg& im)
     return w.c_lo < kPadLo || w.c_hi - kPadLo >= im.W || w.j0 < kPadLo || w.j1 - kPadLo >= im.H;
 }
 
+// Chunk (r, cc) of a window: `px` is its first pixel in the source image
+// (staged, or the caller's image for RAW scans).
 template <typename T, bool RAWOK>
 __device__ __forceinline__ float4 window_chunk(__amdgpu_buffer_rsrc_t rs, const LdsWin& w, int wp, int r, int cc,
-                                               const RawImg& im, bool raw, bool edge)
+                                               uint32_t px, const RawImg& im, bool raw, bool edge)
 {
-    if (!RAWOK || !raw) return Chunk<T>::load(rs, (uint32_t)(__mul24(w.j0 + r, wp) + w.c_lo + 4 * cc));
-    const int j = w.j0 + r - kPadLo, i = w.c_lo - kPadLo + 4 * cc;
-    if (!edge) return Chunk<T>::load(rs, (uint32_t)(__mul24(j, wp) + i));
+    if (!RAWOK || !raw || !edge) return Chunk<T>::load(rs, px);
     // a window reaching past the image: each pixel on its own, off-image ones
     // read as zero (adjacent b32 loads are merged into one multi-dword load,
     // which the buffer range check drops whole when it starts before the
     // image, in-image pixels included)
+    const int j = w.j0 + r - kPadLo, i = w.c_lo - kPadLo + 4 * cc;
     const bool row = (unsigned)j < (unsigned)im.H;
     float v[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const bool ok = row && (unsigned)(i + e) < (unsigned)im.W;
-        const uint32_t px = ok ? (uint32_t)(__mul24(j, wp) + i + e) : 0u;
-        const float x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, px * 4u, 0, 0));
+        const uint32_t q = ok ? (uint32_t)(__mul24(j, wp) + i + e) : 0u;
+        const float x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, q * 4u, 0, 0));
         v[e] = ok ? x : 0.0f;
     }
     return make_float4(v[0], v[1], v[2], v[3]);
 }
 
+// How the threads of a workgroup split a window: thread t copies chunk column
+// cc = t mod nc of rows r0 = t / nc, r0 + R, r0 + 2R, ... with R = NT / nc >= 1
+// rows per pass (a fitting window has nc <= NT; the threads from R * nc on
+// copy nothing), so that from one chunk to the next the source and LDS
+// offsets advance by uniform steps.
 template <typename T, int NW, bool RAWOK = false>
 __device__ __forceinline__ void window_prefetch(Fill& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs, int wp,
                                                 const RawImg& im = RawImg{0, 0}, bool raw = false)
 {
+    constexpr int NT = kWave * NW;
     const bool edge = RAWOK && raw && raw_edge(w, im);
-    // chunk e = t + i * NT of the window, row-major by 4-pixel chunks: row and
-    // column are found once and then stepped by NT
     // (e + 0.5) * rcp(nc) floors to e / nc exactly: the relative error of the
     // product (2 ulp) stays below 0.5 / nc for e, nc < 2^14
-    constexpr int NT = kWave * NW;
     const float inv_nc = __builtin_amdgcn_rcpf((float)w.nc);
-    const int q = (int)(((float)NT + 0.5f) * inv_nc), rm = NT - __mul24(q, w.nc);
-    int e = (int)threadIdx.x;
-    int r = (int)(((float)e + 0.5f) * inv_nc);
-    int cc = e - __mul24(r, w.nc);
+    f.R = __builtin_amdgcn_readfirstlane((int)(((float)NT + 0.5f) * inv_nc));
+    const int t = (int)threadIdx.x;
+    int r0 = (int)(((float)t + 0.5f) * inv_nc);
+    const int cc = t - __mul24(r0, w.nc);
+    if (r0 >= f.R) r0 = w.th;   // idle thread: its rows start past the window
+    const int sh = RAWOK && raw ? kPadLo : 0;
+    f.r0 = r0;
+    f.px0 = (uint32_t)(__mul24(w.j0 + r0 - sh, wp) + w.c_lo - sh + 4 * cc);
+    f.lo0 = __mul24(r0, w.tw) + 4 * cc;
+    // uniform steps, kept opaque so that each chunk's offsets are one add
+    f.dpx = (uint32_t)__builtin_amdgcn_readfirstlane(__mul24(f.R, wp));
+    f.dlo = __builtin_amdgcn_readfirstlane(__mul24(f.R, w.tw));
 #pragma unroll
-    for (int i = 0; i < kPre; ++i) {
-        f.lo[i] = -1;
-        if (e < w.total) {
-            f.v[i] = window_chunk<T, RAWOK>(rs, w, wp, r, cc, im, raw, edge);
-            f.lo[i] = __mul24(r, w.tw) + 4 * cc;
-        }
-        e += NT;
-        r += q;
-        cc += rm;
-        if (cc >= w.nc) {
-            cc -= w.nc;
-            ++r;
-        }
-    }
+    for (int i = 0; i < kPre; ++i)
+        if (r0 + i * f.R < w.th)
+            f.v[i] = window_chunk<T, RAWOK>(rs, w, wp, r0 + i * f.R, cc, f.px0 + (uint32_t)i * f.dpx, im, raw, edge);
 }
 
 template <typename T, int NW, bool RAWOK = false>
@@ -703,16 +712,29 @@ __device__ __forceinline__ void window_store(float* lds, const Fill& f, const Ld
 {
 #pragma unroll
     for (int i = 0; i < kPre; ++i)
-        if (f.lo[i] >= 0) *reinterpret_cast<float4*>(&lds[f.lo[i]]) = f.v[i];
+        if (f.r0 + i * f.R < w.th) *reinterpret_cast<float4*>(&lds[f.lo0 + i * f.dlo]) = f.v[i];
+    // rows past the prefetched ones, loaded and stored here
+    int r = f.r0 + kPre * f.R;
+    if (r >= w.th) return;
     const bool edge = RAWOK && raw && raw_edge(w, im);
-    const float inv_nc = __builtin_amdgcn_rcpf((float)w.nc);
-    for (int e = (int)threadIdx.x + kPre * kWave * NW; e < w.total; e += kWave * NW) {
-        const int r = (int)(((float)e + 0.5f) * inv_nc);
-        const int cc = e - __mul24(r, w.nc);
-        *reinterpret_cast<float4*>(&lds[__mul24(r, w.tw) + 4 * cc]) =
-            window_chunk<T, RAWOK>(rs, w, wp, r, cc, im, raw, edge);
-    }
+    const int cc = (f.lo0 - __mul24(f.r0, w.tw)) >> 2;
+    uint32_t px = f.px0 + (uint32_t)kPre * f.dpx;
+    int lo = f.lo0 + kPre * f.dlo;
+    for (; r < w.th; r += f.R, px += f.dpx, lo += f.dlo)
+        *reinterpret_cast<float4*>(&lds[lo]) = window_chunk<T, RAWOK>(rs, w, wp, r, cc, px, im, raw, edge);
 }
+
+// Window of (tile, projection) from the table written by window_kernel, read
+// through the scalar cache (the table does not change during the launch).
+__device__ __forceinline__ Win load_win(const Win* p)
+{
+    using U64C = const __attribute__((address_space(4))) uint64_t;
+    return __builtin_bit_cast(Win, *(U64C*)p);
+}
+
+// Wait for every vector-memory load of this wave (vmcnt = 0, other counters
+// left alone).
+__device__ __forceinline__ void wait_vm_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // One tile of the LDS backprojection; `lds` is the workgroup's 32 KiB tile.
 // CWM: 1 every projection has w constant along z (one 1/w per strip), 0 none
@@ -759,7 +781,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     // software pipeline: the window of the projection after this one is
     // loaded into registers while this one is sampled from LDS
     Fill pre;
-    LdsWin wv(wins[po.k]);
+    LdsWin wv(load_win(wins + po.k), kWave * NW);
     bool big = false;
     if (wv.fits) window_prefetch<T, NW, RAWOK>(pre, wv, make_rsrc(po.img, a.proj_bytes), wp, im, raw);
     for (int n = 0; n < a.n_proj; ++n) {
@@ -767,7 +789,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
         const unsigned char* img = po.img;
         po.advance(a);
         const bool more = n + 1 < a.n_proj;
-        const LdsWin wn(more ? wins[po.k] : Win{1, 0, 1, 0});
+        const LdsWin wn(more ? load_win(wins + po.k) : Win{1, 0, 1, 0}, kWave * NW);
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
         const __amdgpu_buffer_rsrc_t rs_next = make_rsrc(po.img, a.proj_bytes);
         if (wv.fits) {
@@ -775,6 +797,12 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
             window_store<T, NW, RAWOK>(lds, pre, wv, rs, wp, im, raw);
             __syncthreads();
         }
+        // every chunk of this window is in LDS by now; an unconditional wait
+        // here tells the compiler so, and the next window's loads below are
+        // then issued back to back (after the chunk loads and stores under
+        // per-thread branches it would otherwise wait for each load before
+        // reusing its registers for the next)
+        wait_vm_loads();
         if (wn.fits) window_prefetch<T, NW, RAWOK>(pre, wn, rs_next, wp, im, raw);
         if (wv.fits) {
             const Strip st = strip_setup<2>(cur.c, p, a, wp);
@@ -816,7 +844,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
         // the staged images (kept out of the main loop, which then has a
         // single sampling path)
         for (int k = 0; k < a.n_proj; ++k) {
-            const LdsWin w(wins[k]);
+            const LdsWin w(load_win(wins + k), kWave * NW);
             if (w.fits || w.empty) continue;
             const Coef cur = load_coef(a.coef, k);
             const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.proj + (uint64_t)k * a.proj_stride, a.proj_bytes);
