@@ -551,10 +551,14 @@ __global__ void window_kernel(TileArgs a, int strip, int bx, int by, Win* __rest
 }
 
 // Staged pixels of one LDS chunk (4 consecutive pixels of a row, 16-byte
-// aligned in the staged image), widened to FP32.
+// aligned in the staged image): `load` returns the stored bits (Raw), `widen`
+// turns them into FP32.  The two are kept apart so that a chunk prefetched
+// into registers is converted only when it is stored to LDS, long after its
+// load has landed (converting at once would make the wave wait for it).
 template <typename T> struct Chunk;
 template <> struct Chunk<float> {
-    static __device__ __forceinline__ float4 load(__amdgpu_buffer_rsrc_t r, uint32_t px)
+    using Raw = float4;
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t px)
     {
         const uint32_t o = px * 4;
         return make_float4(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0)),
@@ -562,27 +566,36 @@ template <> struct Chunk<float> {
                            __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o + 8, 0, 0)),
                            __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o + 12, 0, 0)));
     }
+    static __device__ __forceinline__ float4 widen(const Raw& v) { return v; }
 };
 template <> struct Chunk<__half> {
-    static __device__ __forceinline__ float4 load(__amdgpu_buffer_rsrc_t r, uint32_t px)
+    using Raw = uint2;
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t px)
     {
         const uint32_t o = px * 2;
-        const uint32_t a = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
-        const uint32_t b = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o + 4, 0, 0);
-        return make_float4(__half2float(__ushort_as_half((unsigned short)(a & 0xffffu))),
-                           __half2float(__ushort_as_half((unsigned short)(a >> 16))),
-                           __half2float(__ushort_as_half((unsigned short)(b & 0xffffu))),
-                           __half2float(__ushort_as_half((unsigned short)(b >> 16))));
+        return make_uint2((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0),
+                          (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o + 4, 0, 0));
+    }
+    static __device__ __forceinline__ float4 widen(const Raw& v)
+    {
+        return make_float4(__half2float(__ushort_as_half((unsigned short)(v.x & 0xffffu))),
+                           __half2float(__ushort_as_half((unsigned short)(v.x >> 16))),
+                           __half2float(__ushort_as_half((unsigned short)(v.y & 0xffffu))),
+                           __half2float(__ushort_as_half((unsigned short)(v.y >> 16))));
     }
 };
 template <> struct Chunk<bf16_t> {
-    static __device__ __forceinline__ float4 load(__amdgpu_buffer_rsrc_t r, uint32_t px)
+    using Raw = uint2;
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t px)
     {
         const uint32_t o = px * 2;
-        const uint32_t a = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
-        const uint32_t b = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o + 4, 0, 0);
-        return make_float4(__uint_as_float(a << 16), __uint_as_float(a & 0xffff0000u),
-                           __uint_as_float(b << 16), __uint_as_float(b & 0xffff0000u));
+        return make_uint2((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0),
+                          (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o + 4, 0, 0));
+    }
+    static __device__ __forceinline__ float4 widen(const Raw& v)
+    {
+        return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
+                           __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
     }
 };
 
@@ -630,8 +643,9 @@ struct LdsWin {
 // load their remainder after the barrier.
 constexpr int kPre = 4;
 
+template <typename T>
 struct Fill {
-    float4 v[kPre];   // chunk i: row r0 + i * R of this thread's chunk column
+    typename Chunk<T>::Raw v[kPre];   // chunk i: row r0 + i * R of this thread's chunk column
     int r0, lo0;      // first row and its LDS float offset (r0 >= th: none)
     uint32_t px0;     // first chunk's source pixel
     int R, dlo;       // rows per pass and the LDS step per pass (uniform)
@@ -651,27 +665,34 @@ __device__ __forceinline__ bool raw_edge(const LdsWin& w, const RawImg& im)
 }
 
 // Chunk (r, cc) of a window: `px` is its first pixel in the source image
-// (staged, or the caller's image for RAW scans).
+// (staged, or the caller's image for RAW scans, which are FP32).
 template <typename T, bool RAWOK>
-__device__ __forceinline__ float4 window_chunk(__amdgpu_buffer_rsrc_t rs, const LdsWin& w, int wp, int r, int cc,
-                                               uint32_t px, const RawImg& im, bool raw, bool edge)
+__device__ __forceinline__ typename Chunk<T>::Raw window_chunk(__amdgpu_buffer_rsrc_t rs, const LdsWin& w, int wp,
+                                                               int r, int cc, uint32_t px, const RawImg& im,
+                                                               bool raw, bool edge)
 {
-    if (!RAWOK || !raw || !edge) return Chunk<T>::load(rs, px);
-    // a window reaching past the image: each pixel on its own, off-image ones
-    // read as zero (adjacent b32 loads are merged into one multi-dword load,
-    // which the buffer range check drops whole when it starts before the
-    // image, in-image pixels included)
-    const int j = w.j0 + r - kPadLo, i = w.c_lo - kPadLo + 4 * cc;
-    const bool row = (unsigned)j < (unsigned)im.H;
-    float v[4];
+    if constexpr (RAWOK) {
+        static_assert(std::is_same<T, float>::value, "unstaged images are FP32");
+        if (raw && edge) {
+            // a window reaching past the image: each pixel on its own (adjacent
+            // b32 loads are merged into one multi-dword load, which the buffer
+            // range check drops whole when it starts before the image, in-image
+            // pixels included); a pixel off the image is read at the end of
+            // the image's range, which the range check returns as zero
+            const int j = w.j0 + r - kPadLo, i = w.c_lo - kPadLo + 4 * cc;
+            const bool row = (unsigned)j < (unsigned)im.H;
+            const uint32_t end = (uint32_t)__mul24(im.W, im.H) * 4u;
+            float v[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const bool ok = row && (unsigned)(i + e) < (unsigned)im.W;
-        const uint32_t q = ok ? (uint32_t)(__mul24(j, wp) + i + e) : 0u;
-        const float x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, q * 4u, 0, 0));
-        v[e] = ok ? x : 0.0f;
+            for (int e = 0; e < 4; ++e) {
+                const bool ok = row && (unsigned)(i + e) < (unsigned)im.W;
+                const uint32_t o = ok ? (uint32_t)(__mul24(j, wp) + i + e) * 4u : end;
+                v[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o, 0, 0));
+            }
+            return make_float4(v[0], v[1], v[2], v[3]);
+        }
     }
-    return make_float4(v[0], v[1], v[2], v[3]);
+    return Chunk<T>::load(rs, px);
 }
 
 // How the threads of a workgroup split a window: thread t copies chunk column
@@ -680,7 +701,7 @@ __device__ __forceinline__ float4 window_chunk(__amdgpu_buffer_rsrc_t rs, const 
 // copy nothing), so that from one chunk to the next the source and LDS
 // offsets advance by uniform steps.
 template <typename T, int NW, bool RAWOK = false>
-__device__ __forceinline__ void window_prefetch(Fill& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs, int wp,
+__device__ __forceinline__ void window_prefetch(Fill<T>& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs, int wp,
                                                 const RawImg& im = RawImg{0, 0}, bool raw = false)
 {
     constexpr int NT = kWave * NW;
@@ -707,12 +728,12 @@ __device__ __forceinline__ void window_prefetch(Fill& f, const LdsWin& w, __amdg
 }
 
 template <typename T, int NW, bool RAWOK = false>
-__device__ __forceinline__ void window_store(float* lds, const Fill& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs,
+__device__ __forceinline__ void window_store(float* lds, const Fill<T>& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs,
                                              int wp, const RawImg& im = RawImg{0, 0}, bool raw = false)
 {
 #pragma unroll
     for (int i = 0; i < kPre; ++i)
-        if (f.r0 + i * f.R < w.th) *reinterpret_cast<float4*>(&lds[f.lo0 + i * f.dlo]) = f.v[i];
+        if (f.r0 + i * f.R < w.th) *reinterpret_cast<float4*>(&lds[f.lo0 + i * f.dlo]) = Chunk<T>::widen(f.v[i]);
     // rows past the prefetched ones, loaded and stored here
     int r = f.r0 + kPre * f.R;
     if (r >= w.th) return;
@@ -721,7 +742,7 @@ __device__ __forceinline__ void window_store(float* lds, const Fill& f, const Ld
     uint32_t px = f.px0 + (uint32_t)kPre * f.dpx;
     int lo = f.lo0 + kPre * f.dlo;
     for (; r < w.th; r += f.R, px += f.dpx, lo += f.dlo)
-        *reinterpret_cast<float4*>(&lds[lo]) = window_chunk<T, RAWOK>(rs, w, wp, r, cc, px, im, raw, edge);
+        *reinterpret_cast<float4*>(&lds[lo]) = Chunk<T>::widen(window_chunk<T, RAWOK>(rs, w, wp, r, cc, px, im, raw, edge));
 }
 
 // Window of (tile, projection) from the table written by window_kernel, read
@@ -780,7 +801,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     ProjOrder po(a, tile, rot_div);
     // software pipeline: the window of the projection after this one is
     // loaded into registers while this one is sampled from LDS
-    Fill pre;
+    Fill<T> pre;
     LdsWin wv(load_win(wins + po.k), kWave * NW);
     bool big = false;
     if (wv.fits) window_prefetch<T, NW, RAWOK>(pre, wv, make_rsrc(po.img, a.proj_bytes), wp, im, raw);
