@@ -297,8 +297,10 @@ fdk_status fdk_sirt(const fdk_volume* vol, const fdk_projections* proj, float* v
  * projection as a zero-bordered image; layout 1 stores with every staged
  * pixel its whole 2x2 bilinear block (four times the staging memory, one load
  * per sample); layout 2 stores with every pixel its right neighbour (twice the
- * memory, aligned row loads); layout 3 copies each workgroup's projection
- * window into LDS and reads the taps there.  The `dtype` argument selects a
+ * memory, aligned row loads); layout 3 (the built-in choice for every dtype)
+ * copies each workgroup's projection window into LDS and reads the taps there
+ * (a window of more than 8192 pixels, or wider than 4 pixels per thread of
+ * the workgroup, is gathered from the staged image instead).  The `dtype` argument selects a
  * tuning slot: FDK_F32, FDK_F16, FDK_BF16 (backprojection by projection
  * dtype), FDK_TUNE_BATCHED (strip and waves of fdk_backproject_batched, and
  * the layout of its FP32 scans; FP16/BF16 scans keep the layout of their own
