@@ -534,11 +534,17 @@ TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, Til
     a.cu = cu;
     a.cv = cv;
     a.win = nullptr;
+    a.anc = nullptr;
     a.rot_div = 0;
     a.const_w = 0;
     a.raw = 0;
     return a;
 }
+
+// A window table of n entries and its sampling set-ups share one allocation:
+// the windows, then (at a 256-byte boundary) the set-ups.
+size_t anc_offset(uint64_t n) { return (size_t)((n * sizeof(Win) + 255) / 256 * 256); }
+size_t window_table_bytes(uint64_t n) { return anc_offset(n) + (size_t)n * sizeof(Anc); }
 
 fdk_status check_grid(const TileArgs& a)
 {
@@ -696,11 +702,14 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     }
     if (t.layout == 3) {
         const uint64_t nwin = (uint64_t)a.tiles_x * a.tiles_y * a.tiles_z * proj->n_proj;
-        e = ensure(d->windows, nwin * sizeof(Win));
+        e = ensure(d->windows, window_table_bytes(nwin));
         if (e != hipSuccess) return fail(FDK_E_NOMEM, "window table: %s", hipGetErrorString(e));
-        a.win = static_cast<const Win*>(d->windows.p);
+        Win* win = static_cast<Win*>(d->windows.p);
+        Anc* anc = reinterpret_cast<Anc*>(static_cast<unsigned char*>(d->windows.p) + anc_offset(nwin));
+        a.win = win;
+        a.anc = anc;
         ProfScope ps("window", s);
-        HIP_TRY(launch_window(a, t.strip, t.waves, static_cast<Win*>(d->windows.p), s));
+        HIP_TRY(launch_window(a, t.strip, t.waves, win, anc, s));
     }
     {
         ProfScope ps("bp", s);
@@ -1597,7 +1606,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         alloc(b.coef64, coef64.size() * sizeof(double));
         alloc(b.coef_dev, (size_t)total_proj * 16 * sizeof(double));
         alloc(b.counter, sizeof(unsigned));
-        if (win_total > 0) alloc(b.windows, win_total * sizeof(Win));
+        if (win_total > 0) alloc(b.windows, window_table_bytes((uint64_t)win_total));
         if (e != hipSuccess) {
             release_entry(b);
             return fail(FDK_E_NOMEM, "batched tables: %s", hipGetErrorString(e));
@@ -1610,7 +1619,11 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
                                  static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j],
                                  static_cast<double*>(b.coef_dev.p) + (size_t)proj_begin[j] * 16, sc.volume,
                                  out_scales[j], accumulate, sc.proj.dtype);
-            if (win_off[j] >= 0) tiles[j].win = static_cast<const Win*>(b.windows.p) + win_off[j];
+            if (win_off[j] >= 0) {
+                tiles[j].win = static_cast<const Win*>(b.windows.p) + win_off[j];
+                tiles[j].anc = reinterpret_cast<const Anc*>(static_cast<unsigned char*>(b.windows.p) +
+                                                            anc_offset((uint64_t)win_total)) + win_off[j];
+            }
             if (is_raw(&sc.proj)) {   // the caller's unpadded images, row pitch W
                 const uint64_t img = (uint64_t)sc.proj.width * sc.proj.height * 4;
                 tiles[j].proj = static_cast<const unsigned char*>(sc.proj.data);
@@ -1647,8 +1660,8 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
             hipError_t ew = hipSuccess;
             for (int j = 0; j < n_scans && ew == hipSuccess; ++j)
                 if (win_off[j] >= 0)
-                    ew = launch_window(tiles[j], t.strip, t.waves,
-                                       static_cast<Win*>(b.windows.p) + win_off[j], d->capture_stream);
+                    ew = launch_window(tiles[j], t.strip, t.waves, static_cast<Win*>(b.windows.p) + win_off[j],
+                                       const_cast<Anc*>(tiles[j].anc), d->capture_stream);
             if (e2 == hipSuccess) e2 = ew;
             hipError_t e3 = launch_reset_counter(static_cast<unsigned*>(b.counter.p), d->capture_stream);
             hipError_t e4 = launch_bp_batched(static_cast<const TileArgs*>(b.tiles.p),

@@ -22,6 +22,25 @@ struct Win {
     int16_t i0, i1, j0, j1;
 };
 
+// Per (tile, projection) sampling set-up of the LDS backprojection, computed
+// by the window prepass in FP64 and rounded once: the remainders u - au w,
+// v - av w and w at the tile's reference voxel (its centre column, at the
+// middle of its strip of planes) for an integer anchor pixel (au, av) near
+// that voxel's projection, their steps per voxel along x, y and z, and, in
+// the tile's window, the clamp range of the remainders and the byte offset
+// of the anchor pixel.  A lane then only adds its column's offset from the
+// reference voxel in FP32; its remainders stay a few tens of pixels times w.
+struct Anc {
+    float ub, vb, wb;
+    float ux, vx, wx;
+    float uy, vy, wy;
+    float du, dv, dw;
+    float lox, hix, loy, hiy;
+    int32_t base;
+    int32_t pad[3];
+};
+static_assert(sizeof(Anc) == 80, "anchor records are 20 dwords");
+
 // Per-scan arguments of the backprojection / forward-projection tile body.
 // Coordinates inside the kernels are centred: the voxel index is offset by
 // `ctr` on every axis and the detector column/row by (cu, cv) = (W/2, H/2),
@@ -47,6 +66,7 @@ struct TileArgs {
     int32_t dtype;               // fdk_dtype of the staged images
     int32_t layout;              // 0 plain, 1 quad, 2 pair (global gathers), 3 LDS tiles
     const Win* win;              // layout 3: n_tiles x n_proj windows
+    const Anc* anc;              // layout 3: n_tiles x n_proj sampling set-ups (order of win)
     int32_t cu, cv;              // integer detector centre (W/2, H/2)
     int32_t rot_div;             // projection-order rotation divisor (0: every tile starts at k = 0)
     int32_t const_w;             // 1: w does not depend on z for any projection of the launch
@@ -140,7 +160,9 @@ hipError_t launch_unstage_add(const float* padded, float* out, int n, int W, int
                               uint64_t stride_elems, int accumulate, hipStream_t s);
 hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* dst, float* scale,
                        hipStream_t s);
-hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, hipStream_t s);
+// Windows (out) and sampling set-ups (anc, n_tiles x n_proj each) of an LDS
+// launch with the given tile shape.
+hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, Anc* anc, hipStream_t s);
 int supported_tile(int strip, int waves);
 int batched_blocks_per_cu(int strip, int waves);
 

@@ -508,7 +508,7 @@ __global__ __launch_bounds__(kWave * NW)
 // the hull of its corners), widened by one pixel against FP32 rounding in the
 // kernel.  A tile whose footprint misses the detector gets an empty window:
 // the paper's clipping mask at tile granularity.
-__global__ void window_kernel(TileArgs a, int strip, int bx, int by, Win* __restrict__ out)
+__global__ void window_kernel(TileArgs a, int strip, int bx, int by, Win* __restrict__ out, Anc* __restrict__ anc)
 {
     const int64_t n_tiles = (int64_t)a.tiles_x * a.tiles_y * a.tiles_z;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -548,6 +548,41 @@ __global__ void window_kernel(TileArgs a, int strip, int bx, int by, Win* __rest
         wv.j1 = (int16_t)((int)cjh + a.cv + kPadLo);
     }
     out[t] = wv;
+    Anc r = {};
+    if (wv.i0 <= wv.i1) {
+        // reference voxel: the tile's centre column (x0 + 4 bx, y0 + 4 by) at the
+        // middle of its strip, as each lane's strip is anchored at its middle
+        const double X = (double)(x0 + 4 * bx - a.ctr), Y = (double)(y0 + 4 * by - a.ctr);
+        const double Z = (double)(a.z_begin + z0 + strip / 2 - a.ctr);
+        const double u = fma(X, c[0], fma(Y, c[1], fma(Z, c[2], c[3])));
+        const double v = fma(X, c[4], fma(Y, c[5], fma(Z, c[6], c[7])));
+        const double w = fma(X, c[8], fma(Y, c[9], fma(Z, c[10], c[11])));
+        // any integer near u/w will do; clamping keeps the integer math bounded
+        const double fau = fmin(fmax(rint(u / w), (double)a.lo_x), (double)a.hi_x);
+        const double fav = fmin(fmax(rint(v / w), (double)a.lo_y), (double)a.hi_y);
+        r.ub = (float)fma(-fau, w, u);
+        r.vb = (float)fma(-fav, w, v);
+        r.wb = (float)w;
+        r.ux = (float)fma(-fau, c[8], c[0]);
+        r.vx = (float)fma(-fav, c[8], c[4]);
+        r.wx = (float)c[8];
+        r.uy = (float)fma(-fau, c[9], c[1]);
+        r.vy = (float)fma(-fav, c[9], c[5]);
+        r.wy = (float)c[9];
+        r.du = (float)fma(-fau, c[10], c[2]);
+        r.dv = (float)fma(-fav, c[10], c[6]);
+        r.dw = (float)c[10];
+        // anchor in window (staged-pixel) coordinates; the clamp range keeps
+        // both tap columns and rows inside the window held in LDS
+        const int ax = (int)fau + a.cu + kPadLo, ay = (int)fav + a.cv + kPadLo;
+        const int c_lo = wv.i0 & ~3, c_hi = wv.i1 | 3;
+        r.lox = (float)(c_lo - ax);
+        r.hix = (float)(c_hi - 1 - ax);
+        r.loy = (float)(wv.j0 - ay);
+        r.hiy = (float)(wv.j1 - 1 - ay);
+        r.base = ((ay - wv.j0) * (c_hi - c_lo + 1) + (ax - c_lo)) * 4;
+    }
+    anc[t] = r;
 }
 
 // Staged pixels of one LDS chunk (4 consecutive pixels of a row, 16-byte
@@ -753,6 +788,20 @@ __device__ __forceinline__ Win load_win(const Win* p)
     return __builtin_bit_cast(Win, *(U64C*)p);
 }
 
+// Sampling set-up of (tile, projection) from the table written by
+// window_kernel, read through the scalar cache like the windows.
+__device__ __forceinline__ Anc load_anc(const Anc* p)
+{
+    using FC = const __attribute__((address_space(4))) uint32_t;
+    struct Words {
+        uint32_t v[20];
+    } r;
+    FC* q = (FC*)p;
+#pragma unroll
+    for (int i = 0; i < 20; ++i) r.v[i] = q[i];
+    return __builtin_bit_cast(Anc, r);
+}
+
 // Wait for every vector-memory load of this wave (vmcnt = 0, other counters
 // left alone).
 __device__ __forceinline__ void wait_vm_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
@@ -798,6 +847,10 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     const uint32_t row = a.row_bytes;
     const int wp = (int)(a.row_bytes / sizeof(T));
     const Win* wins = a.win + (int64_t)tile * a.n_proj;
+    const Anc* ancs = a.anc + (int64_t)tile * a.n_proj;
+    // the lane's column relative to the tile's reference voxel (its centre column)
+    constexpr int kTX = 8 * Patch<NW>::kBX, kTY = 8 * Patch<NW>::kBY;
+    const float lx = (float)(p.x % kTX - kTX / 2), ly = (float)(p.y % kTY - kTY / 2);
     ProjOrder po(a, tile, rot_div);
     // software pipeline: the window of the projection after this one is
     // loaded into registers while this one is sampled from LDS
@@ -806,7 +859,9 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     bool big = false;
     if (wv.fits) window_prefetch<T, NW, RAWOK>(pre, wv, make_rsrc(po.img, a.proj_bytes), wp, im, raw);
     for (int n = 0; n < a.n_proj; ++n) {
-        const Coef cur = load_coef(a.coef, po.k);
+        // this projection's set-up, loaded ahead of the window store so that
+        // its latency passes behind the barriers
+        const Anc an = load_anc(ancs + po.k);
         const unsigned char* img = po.img;
         po.advance(a);
         const bool more = n + 1 < a.n_proj;
@@ -826,36 +881,67 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
         wait_vm_loads();
         if (wn.fits) window_prefetch<T, NW, RAWOK>(pre, wn, rs_next, wp, im, raw);
         if (wv.fits) {
-            const Strip st = strip_setup<2>(cur.c, p, a, wp);
-            // anchor in staged-pixel coordinates; clamp so both tap columns
-            // and rows stay inside the window held in LDS
-            const float ax = st.fau + (float)(a.cu + kPadLo), ay = st.fav + (float)(a.cv + kPadLo);
-            const float lox = (float)wv.c_lo - ax, hix = (float)(wv.c_hi - 1) - ax;
-            const float loy = (float)wv.j0 - ay, hiy = (float)(wv.j1 - 1) - ay;
-            const int base = (__mul24((int)ay - wv.j0, wv.tw) + ((int)ax - wv.c_lo)) * 4;
+            // the tile's anchor, clamp range and LDS offset are shared by all
+            // lanes; each lane adds its column's offset
+            Strip st;
+            st.ub = fmaf(lx, an.ux, fmaf(ly, an.uy, an.ub));
+            st.vb = fmaf(lx, an.vx, fmaf(ly, an.vy, an.vb));
+            st.wb = fmaf(lx, an.wx, fmaf(ly, an.wy, an.wb));
+            st.du = an.du;
+            st.dv = an.dv;
+            st.dw = an.dw;
+            const float lox = an.lox, hix = an.hix, loy = an.loy, hiy = an.hiy;
+            const int base = an.base;
             const uint32_t row_l = (uint32_t)wv.tw * 4;
             auto sample = [&](auto cw) {
                 const Walk<decltype(cw)::value> wk(st);
+                // kGrp samples at a time: their positions first, then all their
+                // LDS reads, then the interpolations, so that a wave has the
+                // reads of several samples in flight instead of waiting for
+                // each sample's taps in turn
+                constexpr int kGrp = S < 4 ? S : 4;
 #pragma unroll
-                for (int s = 0; s < S; ++s) {
+                for (int g = 0; g < S; g += kGrp) {
                     constexpr int kMid = S / 2;
-                    float ux, uy, wgt;
-                    wk.at((float)(s - kMid), ux, uy, wgt);
-                    const float dx = __builtin_amdgcn_fmed3f(ux, lox, hix);
-                    const float dy = __builtin_amdgcn_fmed3f(uy, loy, hiy);
-                    const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
-                    const uint32_t off = tap_offset<2>(cvt_floor(dx), cvt_floor(dy), wv.tw, base);
-                    const float* q0 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off);
-                    const float* q1 =
-                        reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off + row_l);
-                    const float top = fmaf(sx, q0[1] - q0[0], q0[0]);
-                    const float bot = fmaf(sx, q1[1] - q1[0], q1[0]);
-                    const float val = fmaf(sy, bot - top, top);
-                    acc[s] = fmaf(val, wgt, acc[s]);
+                    uint32_t off[kGrp];
+                    float sx[kGrp], sy[kGrp], wgt[kGrp];
+#pragma unroll
+                    for (int j = 0; j < kGrp; ++j) {
+                        float ux, uy;
+                        wk.at((float)(g + j - kMid), ux, uy, wgt[j]);
+                        const float dx = __builtin_amdgcn_fmed3f(ux, lox, hix);
+                        const float dy = __builtin_amdgcn_fmed3f(uy, loy, hiy);
+                        sx[j] = __builtin_amdgcn_fractf(dx);
+                        sy[j] = __builtin_amdgcn_fractf(dy);
+                        off[j] = tap_offset<2>(cvt_floor(dx), cvt_floor(dy), wv.tw, base);
+                    }
+                    float t00[kGrp], t01[kGrp], t10[kGrp], t11[kGrp];
+#pragma unroll
+                    for (int j = 0; j < kGrp; ++j) {
+                        const float* q0 =
+                            reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off[j]);
+                        const float* q1 =
+                            reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off[j] + row_l);
+                        t00[j] = q0[0];
+                        t01[j] = q0[1];
+                        t10[j] = q1[0];
+                        t11[j] = q1[1];
+                    }
+#pragma unroll
+                    for (int j = 0; j < kGrp; ++j) {
+                        const float top = fmaf(sx[j], t01[j] - t00[j], t00[j]);
+                        const float bot = fmaf(sx[j], t11[j] - t10[j], t10[j]);
+                        const float val = fmaf(sy[j], bot - top, top);
+                        acc[g + j] = fmaf(val, wgt[j], acc[g + j]);
+                    }
                 }
             };
-            if (CWM == 2) with_walk(cur.c, sample);
-            else sample(std::integral_constant<bool, CWM == 1>{});
+            if (CWM == 2) {
+                if (an.dw == 0.0f) sample(std::true_type{});
+                else sample(std::false_type{});
+            } else {
+                sample(std::integral_constant<bool, CWM == 1>{});
+            }
         }
         big |= !wv.fits && !wv.empty;
         wv = wn;
@@ -1392,13 +1478,13 @@ int batched_blocks_per_cu(int strip, int waves)
     return 0;
 }
 
-hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, hipStream_t s)
+hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, Anc* anc, hipStream_t s)
 {
     const int bx = waves >= 16 ? 4 : waves >= 2 ? 2 : 1, by = waves / bx;   // as Patch<NW>
     const int64_t n = (int64_t)a.tiles_x * a.tiles_y * a.tiles_z * a.n_proj;
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(window_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, strip, bx, by, out);
+    hipLaunchKernelGGL(window_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, strip, bx, by, out, anc);
     return hipGetLastError();
 }
 
