@@ -1606,7 +1606,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         alloc(b.coef64, coef64.size() * sizeof(double));
         alloc(b.coef_dev, (size_t)total_proj * 16 * sizeof(double));
         alloc(b.counter, sizeof(unsigned));
-        if (win_total > 0) alloc(b.windows, window_table_bytes((uint64_t)win_total));
+        if (win_total > 0) alloc(b.windows, win_total * sizeof(Win));
         if (e != hipSuccess) {
             release_entry(b);
             return fail(FDK_E_NOMEM, "batched tables: %s", hipGetErrorString(e));
@@ -1619,11 +1619,8 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
                                  static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j],
                                  static_cast<double*>(b.coef_dev.p) + (size_t)proj_begin[j] * 16, sc.volume,
                                  out_scales[j], accumulate, sc.proj.dtype);
-            if (win_off[j] >= 0) {
-                tiles[j].win = static_cast<const Win*>(b.windows.p) + win_off[j];
-                tiles[j].anc = reinterpret_cast<const Anc*>(static_cast<unsigned char*>(b.windows.p) +
-                                                            anc_offset((uint64_t)win_total)) + win_off[j];
-            }
+            // the persistent kernel anchors every lane itself (no set-up table)
+            if (win_off[j] >= 0) tiles[j].win = static_cast<const Win*>(b.windows.p) + win_off[j];
             if (is_raw(&sc.proj)) {   // the caller's unpadded images, row pitch W
                 const uint64_t img = (uint64_t)sc.proj.width * sc.proj.height * 4;
                 tiles[j].proj = static_cast<const unsigned char*>(sc.proj.data);
@@ -1661,7 +1658,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
             for (int j = 0; j < n_scans && ew == hipSuccess; ++j)
                 if (win_off[j] >= 0)
                     ew = launch_window(tiles[j], t.strip, t.waves, static_cast<Win*>(b.windows.p) + win_off[j],
-                                       const_cast<Anc*>(tiles[j].anc), d->capture_stream);
+                                       nullptr, d->capture_stream);
             if (e2 == hipSuccess) e2 = ew;
             hipError_t e3 = launch_reset_counter(static_cast<unsigned*>(b.counter.p), d->capture_stream);
             hipError_t e4 = launch_bp_batched(static_cast<const TileArgs*>(b.tiles.p),

@@ -160,8 +160,9 @@ hipError_t launch_unstage_add(const float* padded, float* out, int n, int W, int
                               uint64_t stride_elems, int accumulate, hipStream_t s);
 hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* dst, float* scale,
                        hipStream_t s);
-// Windows (out) and sampling set-ups (anc, n_tiles x n_proj each) of an LDS
-// launch with the given tile shape.
+// Windows (out) and sampling set-ups (anc, n_tiles x n_proj each; null: none,
+// for the persistent kernel, which anchors every lane itself) of an LDS launch
+// with the given tile shape.
 hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, Anc* anc, hipStream_t s);
 int supported_tile(int strip, int waves);
 int batched_blocks_per_cu(int strip, int waves);

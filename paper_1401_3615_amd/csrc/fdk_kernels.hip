@@ -548,6 +548,7 @@ __global__ void window_kernel(TileArgs a, int strip, int bx, int by, Win* __rest
         wv.j1 = (int16_t)((int)cjh + a.cv + kPadLo);
     }
     out[t] = wv;
+    if (anc == nullptr) return;   // launches that anchor every lane themselves
     Anc r = {};
     if (wv.i0 <= wv.i1) {
         // reference voxel: the tile's centre column (x0 + 4 bx, y0 + 4 by) at the
@@ -847,7 +848,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     const uint32_t row = a.row_bytes;
     const int wp = (int)(a.row_bytes / sizeof(T));
     const Win* wins = a.win + (int64_t)tile * a.n_proj;
-    const Anc* ancs = a.anc + (int64_t)tile * a.n_proj;
+    const Anc* ancs = CWM == 2 ? nullptr : a.anc + (int64_t)tile * a.n_proj;
     // the lane's column relative to the tile's reference voxel (its centre column)
     constexpr int kTX = 8 * Patch<NW>::kBX, kTY = 8 * Patch<NW>::kBY;
     const float lx = (float)(p.x % kTX - kTX / 2), ly = (float)(p.y % kTY - kTY / 2);
@@ -860,8 +861,12 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     if (wv.fits) window_prefetch<T, NW, RAWOK>(pre, wv, make_rsrc(po.img, a.proj_bytes), wp, im, raw);
     for (int n = 0; n < a.n_proj; ++n) {
         // this projection's set-up, loaded ahead of the window store so that
-        // its latency passes behind the barriers
-        const Anc an = load_anc(ancs + po.k);
+        // its latency passes behind the barriers: the tile's anchor record,
+        // or (persistent kernel) the coefficients for per-lane anchors
+        Anc an;
+        Coef cur;
+        if constexpr (CWM == 2) cur = load_coef(a.coef, po.k);
+        else an = load_anc(ancs + po.k);
         const unsigned char* img = po.img;
         po.advance(a);
         const bool more = n + 1 < a.n_proj;
@@ -881,17 +886,34 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
         wait_vm_loads();
         if (wn.fits) window_prefetch<T, NW, RAWOK>(pre, wn, rs_next, wp, im, raw);
         if (wv.fits) {
-            // the tile's anchor, clamp range and LDS offset are shared by all
-            // lanes; each lane adds its column's offset
             Strip st;
-            st.ub = fmaf(lx, an.ux, fmaf(ly, an.uy, an.ub));
-            st.vb = fmaf(lx, an.vx, fmaf(ly, an.vy, an.vb));
-            st.wb = fmaf(lx, an.wx, fmaf(ly, an.wy, an.wb));
-            st.du = an.du;
-            st.dv = an.dv;
-            st.dw = an.dw;
-            const float lox = an.lox, hix = an.hix, loy = an.loy, hiy = an.hiy;
-            const int base = an.base;
+            float lox, hix, loy, hiy;
+            int base;
+            if constexpr (CWM == 2) {
+                // per-lane anchor at the strip's middle voxel; clamp so both
+                // tap columns and rows stay inside the window held in LDS
+                st = strip_setup<2>(cur.c, p, a, wp);
+                const float ax = st.fau + (float)(a.cu + kPadLo), ay = st.fav + (float)(a.cv + kPadLo);
+                lox = (float)wv.c_lo - ax;
+                hix = (float)(wv.c_hi - 1) - ax;
+                loy = (float)wv.j0 - ay;
+                hiy = (float)(wv.j1 - 1) - ay;
+                base = (__mul24((int)ay - wv.j0, wv.tw) + ((int)ax - wv.c_lo)) * 4;
+            } else {
+                // the tile's anchor, clamp range and LDS offset are shared by
+                // all lanes; each lane adds its column's offset
+                st.ub = fmaf(lx, an.ux, fmaf(ly, an.uy, an.ub));
+                st.vb = fmaf(lx, an.vx, fmaf(ly, an.vy, an.vb));
+                st.wb = fmaf(lx, an.wx, fmaf(ly, an.wy, an.wb));
+                st.du = an.du;
+                st.dv = an.dv;
+                st.dw = an.dw;
+                lox = an.lox;
+                hix = an.hix;
+                loy = an.loy;
+                hiy = an.hiy;
+                base = an.base;
+            }
             const uint32_t row_l = (uint32_t)wv.tw * 4;
             auto sample = [&](auto cw) {
                 const Walk<decltype(cw)::value> wk(st);
@@ -936,9 +958,8 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
                     }
                 }
             };
-            if (CWM == 2) {
-                if (an.dw == 0.0f) sample(std::true_type{});
-                else sample(std::false_type{});
+            if constexpr (CWM == 2) {
+                with_walk(cur.c, sample);
             } else {
                 sample(std::integral_constant<bool, CWM == 1>{});
             }
