@@ -316,6 +316,71 @@ def test_supported_update_count_matches_paper_workload():
     assert 0 < n <= 64 * 64 * 4 * 8
 
 
+@pytest.mark.parametrize("L,W,H,seed", [(4, 7, 5, 1), (5, 7, 5, 2), (8, 7, 5, 3), (6, 5, 7, 4)])
+def test_supported_updates_bruteforce(L, W, H, seed):
+    """The supported-update count (the clipped updates behind the paper's GUp/s,
+    Sec. "Performance Model") equals, exactly, the number of (voxel,
+    projection) pairs with at least one nonzero entry of the dense tent matrix
+    over every pixel, i.e. pairs whose bilinear sample has a tap on the
+    detector.  The tiny cones put voxels at ix in (-1, 0) and (W-1, W), which a
+    support test of [0, W) or [0, W-1] would miss."""
+    voxel = 1.0
+    mats = S.tiny_cone_matrices(3, W, H, L, voxel, seed)
+    ix, iy, _ = pixel_coords(L, voxel, mats)
+    assert (((ix > -1) & (ix < 0)) | ((iy > -1) & (iy < 0))).any()
+    assert (((ix > W - 1) & (ix < W)) | ((iy > H - 1) & (iy < H))).any()
+    B = dense_B(L, voxel, mats, W, H).reshape(L ** 3, 3, H * W)
+    expect = int(np.count_nonzero((B != 0).any(axis=2)))
+    assert 0 < expect < L ** 3 * 3
+    assert oracle.supported_updates(L, voxel, mats, W, H) == expect
+    # per slab of planes, and the slabs add up
+    z = L // 2
+    Bz = B.reshape(L, L * L, 3, H * W)
+    lo = int(np.count_nonzero((Bz[:z] != 0).any(axis=3)))
+    hi = int(np.count_nonzero((Bz[z:] != 0).any(axis=3)))
+    assert oracle.supported_updates(L, voxel, mats, W, H, z_range=(0, z)) == lo
+    assert oracle.supported_updates(L, voxel, mats, W, H, z_range=(z, L - z)) == hi
+    assert lo + hi == expect
+
+
+def test_supported_updates_edges_exact():
+    """Single voxels placed by an affine map at chosen detector coordinates:
+    a sample at ix in (-1, 0) or (W-1, W) (one tap column on the detector)
+    counts, ix = -1 or ix = W exactly (both taps at weight 0 or off) does
+    not, and likewise along the rows."""
+    W, H = 6, 4
+    cases = [((-0.5, 1.0), 1), ((W - 0.5, 1.0), 1), ((-1.0, 1.0), 0), ((float(W), 1.0), 0),
+             ((2.0, -0.25), 1), ((2.0, H - 0.75), 1), ((2.0, -1.0), 0), ((2.0, float(H)), 0),
+             ((-1.5, 2.0), 0), ((2.5, 1.5), 1), ((-0.999, -0.999), 1)]
+    for (u, v), want in cases:
+        A = np.array([[[0, 0, 0, u], [0, 0, 0, v], [0, 0, 0, 1.0]]])
+        assert oracle.supported_updates(1, 1.0, A, W, H) == want, (u, v)
+    # w != 1: the test is on u/w, not on u
+    A = np.array([[[0, 0, 0, -0.5 * 3.0], [0, 0, 0, 1.0 * 3.0], [0, 0, 0, 3.0]]])
+    assert oracle.supported_updates(1, 1.0, A, W, H) == 1
+
+
+def test_psnr_and_rel_l2_hand_values():
+    """PSNR = 10 log10((max ref - min ref)^2 / MSE) and rel L2 = ||x - ref|| /
+    ||ref|| (the quality measures of the paper's benchmark, defined here as
+    their textbook forms) on values worked out by hand."""
+    ref = np.array([1.0, 2.0, 5.0, -3.0])
+    x = np.array([1.0, 4.0, 5.0, -2.0])          # errors 0, 2, 0, 1: MSE = 5/4
+    # range 8: 10 log10(64 / 1.25) = 10 log10(51.2)
+    assert oracle.psnr(x, ref) == pytest.approx(17.092699609758306, abs=1e-12)
+    # ||(0, 2, 0, 1)|| / ||(1, 2, 5, -3)|| = sqrt(5) / sqrt(39)
+    assert oracle.rel_l2(x, ref) == pytest.approx(np.sqrt(5.0 / 39.0), rel=1e-14)
+    # a constant offset d gives MSE = d^2: PSNR = 20 log10(range / d)
+    ref2 = np.linspace(-4.0, 6.0, 101).reshape(101, 1)
+    assert oracle.psnr(ref2 + 0.01, ref2) == pytest.approx(60.0, abs=1e-9)
+    assert oracle.psnr(ref2 - 0.1, ref2) == pytest.approx(40.0, abs=1e-9)
+    # equal inputs: infinite PSNR, zero error
+    assert oracle.psnr(ref, ref) == float("inf")
+    assert oracle.rel_l2(ref, ref) == 0.0
+    # shape does not matter (all voxels in one sum)
+    assert oracle.psnr(x.reshape(2, 2), ref.reshape(2, 2)) == oracle.psnr(x, ref)
+
+
 # ----------------------------------------------------------------------------- FDK preprocessing
 def _filter_args(carm):
     cu, cv = carm.principal_point
