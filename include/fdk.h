@@ -26,8 +26,25 @@
  *   - host arrays (matrices, descriptors) are read before the call returns;
  *   - device pointers belong to the current HIP device;
  *   - work is enqueued on the given HIP stream (NULL = the null stream) and
- *     the call returns without waiting; results are valid once the stream has
- *     been synchronised;
+ *     the call returns without waiting for it; results are valid once the
+ *     stream has been synchronised.  The host does wait in these cases only:
+ *       . a workspace buffer grows (the first call needing a larger one):
+ *         freeing the old buffer synchronises the device;
+ *       . a projector call whose geometry is not among the 64 most recently
+ *         used ones recycles the oldest coefficient table: the host waits
+ *         for the queued work that last read it (usually long finished);
+ *       . fdk_backproject_batched with descriptors not in its graph cache
+ *         uploads its tables and builds the graph (waits for the stream;
+ *         evicting one of the 4 cached graphs, or growing its staging
+ *         buffer, synchronises the device);
+ *       . fdk_filter_projections with a geometry not among the 4 most
+ *         recent ones uploads its tables (waits for the stream; evicting
+ *         one synchronises the device);
+ *       . fdk_backproject_streamed: pageable host memory is copied
+ *         synchronously by the runtime; with a device stack the host waits
+ *         until the previous streamed call has read its band table;
+ *       . fdk_cgls / fdk_sirt as the projectors, plus their own workspace;
+ *       . fdk_release_workspace and fdk_profile_read.
  *   - the library keeps one device workspace per device (projection staging,
  *     coefficient tables, counters).  Calls issued on different streams of one
  *     device are ordered by the library (a call on a new stream first waits for
@@ -83,8 +100,13 @@ typedef struct fdk_volume {
 } fdk_volume;
 
 /* A projection stack: one 3x4 matrix and one width x height image per
- * projection.  For FDK_F16 / FDK_BF16 data the stored value of projection k is
- * p / scale[k] (see fdk_pack_projections); the library multiplies it back.
+ * projection.  With a scale array, projection k contributes scale[k] times
+ * its stored values (for FDK_F16 / FDK_BF16 data packed by
+ * fdk_pack_projections, the stored value is p / scale[k], so the product is
+ * p again).  Any finite factor is exact up to rounding: a zero factor adds
+ * nothing, a negative one subtracts the projection; a non-finite factor gives
+ * unspecified values in the voxels that projection reaches.  The factors are
+ * read on the device, by the call's own work on its stream.
  * fdk_forwardproject uses only n_proj, width, height and mats. */
 typedef struct fdk_projections {
     int32_t n_proj;        /* N >= 1 */
@@ -93,7 +115,7 @@ typedef struct fdk_projections {
     int32_t dtype;         /* fdk_dtype of data */
     const double* mats;    /* HOST, n_proj * 12 float64, row-major per projection */
     const void* data;      /* DEVICE, [n_proj][height][width] of dtype */
-    const float* scale;    /* DEVICE, n_proj float32 dequantisation factors, or NULL for 1 */
+    const float* scale;    /* DEVICE, n_proj float32 factors (finite, any sign), or NULL for 1 */
 } fdk_projections;
 
 /* One scan of a batch. */

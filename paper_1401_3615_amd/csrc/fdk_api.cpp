@@ -298,12 +298,69 @@ void release(DevBuf& b)
     b.n = 0;
 }
 
+// Pinned host memory (uploads from it run asynchronously).
+struct HostBuf {
+    void* p = nullptr;
+    size_t n = 0;
+};
+
+hipError_t ensure_host(HostBuf& b, size_t bytes)
+{
+    if (b.n >= bytes && b.p != nullptr) return hipSuccess;
+    if (b.p != nullptr) {
+        hipError_t e = hipHostFree(b.p);
+        b.p = nullptr;
+        b.n = 0;
+        if (e != hipSuccess) return e;
+    }
+    size_t want = std::max<size_t>(bytes, 4096);
+    hipError_t e = hipHostMalloc(&b.p, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return e;
+    }
+    b.n = want;
+    return hipSuccess;
+}
+
+void release_host(HostBuf& b)
+{
+    if (b.p != nullptr) (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+}
+
+// Composed coefficients of one geometry (one slab, or every slab of an
+// out-of-core call, 12 doubles per projection each), uploaded from a pinned
+// host copy without waiting; `used` is recorded after the last kernel that
+// reads the device table, so an entry is recycled only once that has run.
+struct CoefSlab {
+    const double* dev;   // n_proj * 12 doubles
+    float out_scale;
+    int const_w;
+};
+
 struct CoefEntry {
     std::string key;
     DevBuf buf;
-    float out_scale;
-    bool const_w;
+    HostBuf host;
+    hipEvent_t used = nullptr;
+    std::vector<float> out_scale;   // per slab
+    std::vector<int> const_w;       // per slab
+    size_t slab_doubles = 0;        // doubles per slab in buf
+    CoefSlab slab(size_t i) const
+    {
+        return CoefSlab{static_cast<const double*>(buf.p) + i * slab_doubles, out_scale[i], const_w[i]};
+    }
 };
+
+void release_coef(CoefEntry& c)
+{
+    release(c.buf);
+    release_host(c.host);
+    if (c.used) (void)hipEventDestroy(c.used);
+    c.used = nullptr;
+}
 
 struct BatchEntry {
     std::string key;
@@ -351,8 +408,11 @@ struct DeviceState {
     // a host-to-device and a device-to-host copy stream, and the events that
     // order the buffers between the streams (kept across calls)
     DevBuf band[2], slab[2], band_j0;
+    HostBuf band_j0_host;   // pinned source of the band_j0 upload
     hipStream_t h2d = nullptr, d2h = nullptr;
     hipEvent_t band_ready[2] = {}, band_free[2] = {}, slab_done[2] = {}, slab_free[2] = {};
+    hipEvent_t call_start = nullptr, j0_read = nullptr;
+    bool j0_pending = false;
     bool band_used[2] = {false, false}, slab_used[2] = {false, false};
 };
 
@@ -361,7 +421,7 @@ std::recursive_mutex g_mu;
 std::map<int, DeviceState> g_dev;
 Tuning g_tune;
 
-constexpr size_t kCoefCacheMax = 16;
+constexpr size_t kCoefCacheMax = 64;
 constexpr size_t kBatchCacheMax = 4;
 
 fdk_status device_state(DeviceState** out)
@@ -414,46 +474,73 @@ std::string coef_key(const fdk_volume* v, const fdk_projections* p)
     return k;
 }
 
-// Device copy of the composed FP64 coefficients, cached by geometry content.
-fdk_status coef_table(DeviceState& d, const fdk_volume* v, const fdk_projections* p, hipStream_t s,
-                      const double** dev, float* out_scale, int* const_w = nullptr)
+// Device copy of the composed FP64 coefficients of one or more slabs, cached
+// by content.  A miss composes into the entry's pinned host buffer and
+// uploads asynchronously on `s`; no host wait unless the least recently used
+// entry, recycled for it, is still being read by queued work (then the host
+// waits for that work), or a buffer has to grow (hipFree and hipHostFree
+// synchronise the device).  The caller records `used` after its fold kernel.
+fdk_status coef_lookup(DeviceState& d, const std::string& key, hipStream_t s,
+                       const std::vector<std::pair<const fdk_volume*, const fdk_projections*>>& slabs,
+                       CoefEntry** out)
 {
-    std::string key = coef_key(v, p);
     for (auto it = d.coef_cache.begin(); it != d.coef_cache.end(); ++it) {
         if (it->key == key) {
             d.coef_cache.splice(d.coef_cache.begin(), d.coef_cache, it);
-            *dev = static_cast<const double*>(d.coef_cache.front().buf.p);
-            *out_scale = d.coef_cache.front().out_scale;
-            if (const_w) *const_w = d.coef_cache.front().const_w;
+            *out = &d.coef_cache.front();
             return FDK_OK;
         }
     }
-    Composed c = compose(v, p);
-    for (double x : c.coef)
-        if (!std::isfinite((float)x))
-            return fail(FDK_E_INVALID_ARG, "composed projection matrix exceeds FP32 range");
-    if (d.coef_cache.size() >= kCoefCacheMax) {
-        HIP_TRY(hipDeviceSynchronize());
-        release(d.coef_cache.back().buf);
-        d.coef_cache.pop_back();
+    std::vector<Composed> cs;
+    cs.reserve(slabs.size());
+    size_t per = 0;
+    for (const auto& sl : slabs) {
+        cs.push_back(compose(sl.first, sl.second));
+        for (double x : cs.back().coef)
+            if (!std::isfinite((float)x))
+                return fail(FDK_E_INVALID_ARG, "composed projection matrix exceeds FP32 range");
+        per = std::max(per, cs.back().coef.size());
     }
     CoefEntry e;
-    e.key = std::move(key);
-    e.out_scale = c.out_scale;
-    e.const_w = c.const_w;
-    hipError_t err = ensure(e.buf, c.coef.size() * sizeof(double));
-    if (err != hipSuccess) return fail(FDK_E_NOMEM, "coefficient table allocation failed: %s", hipGetErrorString(err));
-    err = hipMemcpyAsync(e.buf.p, c.coef.data(), c.coef.size() * sizeof(double), hipMemcpyHostToDevice, s);
-    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (d.coef_cache.size() >= kCoefCacheMax) {
+        e = std::move(d.coef_cache.back());
+        d.coef_cache.pop_back();
+        if (e.used) HIP_TRY(hipEventSynchronize(e.used));
+    }
+    if (e.used == nullptr) HIP_TRY(hipEventCreateWithFlags(&e.used, hipEventDisableTiming));
+    const size_t bytes = per * cs.size() * sizeof(double);
+    hipError_t err = ensure(e.buf, bytes);
+    if (err == hipSuccess) err = ensure_host(e.host, bytes);
     if (err != hipSuccess) {
-        release(e.buf);
+        release_coef(e);
+        return fail(FDK_E_NOMEM, "coefficient table allocation failed: %s", hipGetErrorString(err));
+    }
+    e.key = key;
+    e.slab_doubles = per;
+    e.out_scale.clear();
+    e.const_w.clear();
+    double* h = static_cast<double*>(e.host.p);
+    for (size_t i = 0; i < cs.size(); ++i) {
+        std::copy(cs[i].coef.begin(), cs[i].coef.end(), h + i * per);
+        e.out_scale.push_back(cs[i].out_scale);
+        e.const_w.push_back(cs[i].const_w ? 1 : 0);
+    }
+    err = hipMemcpyAsync(e.buf.p, e.host.p, bytes, hipMemcpyHostToDevice, s);
+    // until the table has been read, recycling this entry must wait for the upload
+    if (err == hipSuccess) err = hipEventRecord(e.used, s);
+    if (err != hipSuccess) {
+        release_coef(e);
         return fail(FDK_E_DEVICE, "coefficient upload failed: %s", hipGetErrorString(err));
     }
     d.coef_cache.push_front(std::move(e));
-    *dev = static_cast<const double*>(d.coef_cache.front().buf.p);
-    *out_scale = d.coef_cache.front().out_scale;
-    if (const_w) *const_w = d.coef_cache.front().const_w;
+    *out = &d.coef_cache.front();
     return FDK_OK;
+}
+
+fdk_status coef_table(DeviceState& d, const fdk_volume* v, const fdk_projections* p, hipStream_t s,
+                      CoefEntry** out)
+{
+    return coef_lookup(d, coef_key(v, p), s, {{v, p}}, out);
 }
 
 // Bytes of one staged pixel: the source element (plain), its 2x2 block (quad)
@@ -643,14 +730,18 @@ fdk_status fdk_validate(const fdk_volume* vol, const fdk_projections* proj, int 
     return check_geometry(vol, proj);
 }
 
-fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, float* volume,
-                           int accumulate, void* stream)
+}  // extern "C": host helpers below have C++ linkage
+
+namespace {
+
+// The backprojection of one (slab of a) volume.  `pre`: the slab's composed
+// coefficients from a table the caller owns (out-of-core calls compose all
+// their slabs at once), or null to look them up by geometry.  `used`: where
+// the caller wants an event recorded once the coefficients have been read.
+fdk_status backproject_impl(const fdk_volume* vol, const fdk_projections* proj, float* volume, int accumulate,
+                            hipStream_t s, const CoefSlab* pre, hipEvent_t used)
 {
-    fdk_status st = fdk_validate(vol, proj, 1);
-    if (st != FDK_OK) return st;
-    if (volume == nullptr) return fail(FDK_E_INVALID_ARG, "volume buffer is NULL");
-    std::lock_guard<std::recursive_mutex> lock(g_mu);
-    load_env_tuning();
+    fdk_status st;
     const int es = esize_of(proj->dtype);
     const TileShape t = fit_layout(pick_tile(vol->L, proj->dtype), proj, es);
     TileArgs probe = make_args(vol, proj, es, t, nullptr, nullptr, volume, 1.0f, accumulate, proj->dtype);
@@ -658,7 +749,6 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
 
     DeviceState* d = nullptr;
     if ((st = device_state(&d)) != FDK_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = begin_call(*d, s)) != FDK_OK) return st;
     // FP32 stacks sampled from LDS windows can be read in place (bounds-checked
     // window loads, ~2.5% slower per sample than from the zero-bordered
@@ -675,10 +765,14 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     }
     e = ensure(d->coef_dev, (size_t)proj->n_proj * 16 * sizeof(double));
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "coefficient workspace: %s", hipGetErrorString(e));
-    const double* coef64 = nullptr;
-    float out_scale = 1.0f;
-    int const_w = 0;
-    if ((st = coef_table(*d, vol, proj, s, &coef64, &out_scale, &const_w)) != FDK_OK) return st;
+    CoefSlab cf;
+    CoefEntry* ce = nullptr;
+    if (pre != nullptr) {
+        cf = *pre;
+    } else {
+        if ((st = coef_table(*d, vol, proj, s, &ce)) != FDK_OK) return st;
+        cf = ce->slab(0);
+    }
 
     if (!raw) {
         StageArgs sa = make_stage(proj, es, t.layout, static_cast<unsigned char*>(d->staged.p), 0);
@@ -687,11 +781,13 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     }
     {
         ProfScope ps("fold", s);
-        HIP_TRY(launch_fold_single(coef64, proj->scale, static_cast<double*>(d->coef_dev.p), proj->n_proj, s));
+        HIP_TRY(launch_fold_single(cf.dev, proj->scale, static_cast<double*>(d->coef_dev.p), proj->n_proj, s));
     }
+    if (ce != nullptr) HIP_TRY(hipEventRecord(ce->used, s));
+    if (used != nullptr) HIP_TRY(hipEventRecord(used, s));
     TileArgs a = make_args(vol, proj, es, t, static_cast<unsigned char*>(d->staged.p),
-                           static_cast<double*>(d->coef_dev.p), volume, out_scale, accumulate, proj->dtype);
-    a.const_w = const_w;
+                           static_cast<double*>(d->coef_dev.p), volume, cf.out_scale, accumulate, proj->dtype);
+    a.const_w = cf.const_w;
     if (raw) {   // the caller's unpadded images, row pitch W
         const uint64_t img = (uint64_t)proj->width * proj->height * 4;
         a.proj = static_cast<const unsigned char*>(proj->data);
@@ -718,6 +814,21 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     return end_call(*d, s);
 }
 
+}  // namespace
+
+extern "C" {
+
+fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, float* volume,
+                           int accumulate, void* stream)
+{
+    fdk_status st = fdk_validate(vol, proj, 1);
+    if (st != FDK_OK) return st;
+    if (volume == nullptr) return fail(FDK_E_INVALID_ARG, "volume buffer is NULL");
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
+    load_env_tuning();
+    return backproject_impl(vol, proj, volume, accumulate, static_cast<hipStream_t>(stream), nullptr, nullptr);
+}
+
 // Forward projection by detector-tile ownership: each workgroup owns t.strip
 // detector rows (as many columns as fit its LDS) of t.waves projections and
 // writes them once, straight into the caller's stack.
@@ -738,15 +849,16 @@ static fdk_status forwardproject_tiles(const fdk_volume* vol, const float* volum
     if ((st = begin_call(*d, s)) != FDK_OK) return st;
     hipError_t e = ensure(d->coef_dev, (size_t)geom->n_proj * 16 * sizeof(double));
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "coefficient workspace: %s", hipGetErrorString(e));
-    const double* coef64 = nullptr;
-    float out_scale = 1.0f;
-    int const_w = 0;
-    if ((st = coef_table(*d, vol, geom, s, &coef64, &out_scale, &const_w)) != FDK_OK) return st;
+    CoefEntry* ce = nullptr;
+    if ((st = coef_table(*d, vol, geom, s, &ce)) != FDK_OK) return st;
+    const CoefSlab cf = ce->slab(0);
     {
         ProfScope ps("fold", s);
-        HIP_TRY(launch_fold_single(coef64, nullptr, static_cast<double*>(d->coef_dev.p), geom->n_proj, s));
+        HIP_TRY(launch_fold_single(cf.dev, nullptr, static_cast<double*>(d->coef_dev.p), geom->n_proj, s));
     }
-    b.const_w = const_w;
+    HIP_TRY(hipEventRecord(ce->used, s));
+    const float out_scale = cf.out_scale;
+    b.const_w = cf.const_w;
     b.coef = static_cast<const double*>(d->coef_dev.p);
     b.vol = volume;
     b.out = proj_out;
@@ -791,9 +903,10 @@ fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const 
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "adjoint workspace: %s", hipGetErrorString(e));
     e = ensure(d->coef_dev, (size_t)geom->n_proj * 16 * sizeof(double));
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "coefficient workspace: %s", hipGetErrorString(e));
-    const double* coef64 = nullptr;
-    float out_scale = 1.0f;
-    if ((st = coef_table(*d, vol, geom, s, &coef64, &out_scale)) != FDK_OK) return st;
+    CoefEntry* ce = nullptr;
+    if ((st = coef_table(*d, vol, geom, s, &ce)) != FDK_OK) return st;
+    const CoefSlab cf = ce->slab(0);
+    const float out_scale = cf.out_scale;
 
     {
         ProfScope ps("fill", s);
@@ -801,8 +914,9 @@ fdk_status fdk_forwardproject(const fdk_volume* vol, const float* volume, const 
     }
     {
         ProfScope ps("fold", s);
-        HIP_TRY(launch_fold_single(coef64, nullptr, static_cast<double*>(d->coef_dev.p), geom->n_proj, s));
+        HIP_TRY(launch_fold_single(cf.dev, nullptr, static_cast<double*>(d->coef_dev.p), geom->n_proj, s));
     }
+    HIP_TRY(hipEventRecord(ce->used, s));
     TileArgs a = make_args(vol, geom, 4, t, static_cast<unsigned char*>(d->adjoint.p),
                            static_cast<double*>(d->coef_dev.p), const_cast<float*>(volume), out_scale, 0,
                            FDK_F32);
@@ -1291,6 +1405,8 @@ fdk_status stream_init(DeviceState& d)
             HIP_TRY(hipEventCreateWithFlags(&d.slab_done[b], hipEventDisableTiming));
             HIP_TRY(hipEventCreateWithFlags(&d.slab_free[b], hipEventDisableTiming));
         }
+        HIP_TRY(hipEventCreateWithFlags(&d.call_start, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&d.j0_read, hipEventDisableTiming));
     }
     return FDK_OK;
 }
@@ -1340,6 +1456,31 @@ fdk_status fdk_backproject_streamed(const fdk_volume* vol, const fdk_projections
         if (e == hipSuccess && host_vol) e = ensure(d->slab[b], (size_t)slab_planes * plane * 4);
         if (e != hipSuccess) return fail(FDK_E_NOMEM, "streaming buffers: %s", hipGetErrorString(e));
     }
+    // every slab's coefficients composed and uploaded at once (one cache entry)
+    CoefEntry* ce = nullptr;
+    {
+        std::string key = coef_key(vol, proj);
+        key.append("streamed", 8);
+        key.append(reinterpret_cast<const char*>(&vol->z_begin), 2 * sizeof(int32_t));
+        key.append(reinterpret_cast<const char*>(&slab_planes), sizeof(int32_t));
+        std::vector<fdk_volume> svs(plan.size());
+        std::vector<fdk_projections> bps(plan.size());
+        std::vector<std::pair<const fdk_volume*, const fdk_projections*>> slabs;
+        for (size_t i = 0; i < plan.size(); ++i) {
+            svs[i] = *vol;
+            svs[i].z_begin = plan[i].z0;
+            svs[i].z_count = plan[i].nz;
+            bps[i] = *proj;
+            bps[i].height = plan[i].rows;
+            bps[i].mats = plan[i].mats.data();
+            slabs.emplace_back(&svs[i], &bps[i]);
+        }
+        if ((st = coef_lookup(*d, key, cs, slabs, &ce)) != FDK_OK) return st;
+    }
+    // the library's copy stream starts with the work the caller enqueued
+    // before this call (the stack may be written by it)
+    HIP_TRY(hipEventRecord(d->call_start, cs));
+    HIP_TRY(hipStreamWaitEvent(d->h2d, d->call_start, 0));
     const unsigned char* src = static_cast<const unsigned char*>(proj->data);
     unsigned char* hvol = reinterpret_cast<unsigned char*>(volume);
     // a stack in device memory is gathered by one kernel per slab (the band
@@ -1354,10 +1495,19 @@ fdk_status fdk_backproject_streamed(const fdk_volume* vol, const fdk_projections
         std::vector<int32_t> j0s;
         j0s.reserve(plan.size() * (size_t)N);
         for (const SlabPlan& sp : plan) j0s.insert(j0s.end(), sp.j0.begin(), sp.j0.end());
-        HIP_TRY(hipStreamSynchronize(d->h2d));   // earlier gathers may still read the table
-        hipError_t e = ensure(d->band_j0, j0s.size() * sizeof(int32_t));
+        // the pinned source of the previous upload may still be unread, and a
+        // table that must grow may still be read by earlier gathers
+        if (d->j0_pending) HIP_TRY(hipEventSynchronize(d->j0_read));
+        const size_t jb = j0s.size() * sizeof(int32_t);
+        if (d->band_j0.n < jb) HIP_TRY(hipStreamSynchronize(d->h2d));
+        hipError_t e = ensure(d->band_j0, jb);
+        if (e == hipSuccess) e = ensure_host(d->band_j0_host, jb);
         if (e != hipSuccess) return fail(FDK_E_NOMEM, "band table: %s", hipGetErrorString(e));
-        HIP_TRY(hipMemcpy(d->band_j0.p, j0s.data(), j0s.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        std::memcpy(d->band_j0_host.p, j0s.data(), jb);
+        // ordered after the earlier gathers on the same stream
+        HIP_TRY(hipMemcpyAsync(d->band_j0.p, d->band_j0_host.p, jb, hipMemcpyHostToDevice, d->h2d));
+        HIP_TRY(hipEventRecord(d->j0_read, d->h2d));
+        d->j0_pending = true;
     }
 
     auto enqueue_in = [&](size_t s) -> fdk_status {
@@ -1399,7 +1549,10 @@ fdk_status fdk_backproject_streamed(const fdk_volume* vol, const fdk_projections
         bp.data = d->band[b].p;
         float* out = host_vol ? static_cast<float*>(d->slab[b].p)
                               : volume + (size_t)(sp.z0 - vol->z_begin) * plane;
-        if ((st = fdk_backproject(&sv, &bp, out, accumulate, cs)) != FDK_OK) return st;
+        const CoefSlab cf = ce->slab(s);
+        if ((st = backproject_impl(&sv, &bp, out, accumulate, cs, &cf,
+                                   s + 1 == plan.size() ? ce->used : nullptr)) != FDK_OK)
+            return st;
         HIP_TRY(hipEventRecord(d->band_free[b], cs));
         d->band_used[b] = true;
         if (host_vol) {
@@ -1791,7 +1944,7 @@ fdk_status fdk_release_workspace(void)
     release(d.coef_dev);
     release(d.adjoint);
     release(d.windows);
-    for (CoefEntry& c : d.coef_cache) release(c.buf);
+    for (CoefEntry& c : d.coef_cache) release_coef(c);
     d.coef_cache.clear();
     for (BatchEntry& b : d.batch_cache) {
         release_entry(b);
@@ -1810,6 +1963,8 @@ fdk_status fdk_release_workspace(void)
         d.band_used[b] = d.slab_used[b] = false;
     }
     release(d.band_j0);
+    release_host(d.band_j0_host);
+    d.j0_pending = false;
     d.have_last = false;
     return FDK_OK;
 }

@@ -30,6 +30,8 @@ struct Win {
 // the tile's window, the clamp range of the remainders and the byte offset
 // of the anchor pixel.  A lane then only adds its column's offset from the
 // reference voxel in FP32; its remainders stay a few tens of pixels times w.
+// The sign of the projection's dequantisation factor rides along (its
+// magnitude is folded into w; a zero factor gives an empty window).
 struct Anc {
     float ub, vb, wb;
     float ux, vx, wx;
@@ -37,7 +39,8 @@ struct Anc {
     float du, dv, dw;
     float lox, hix, loy, hiy;
     int32_t base;
-    int32_t pad[3];
+    int32_t neg;       // 1: the projection's dequantisation factor is negative
+    int32_t pad[2];
 };
 static_assert(sizeof(Anc) == 80, "anchor records are 20 dwords");
 
@@ -49,6 +52,8 @@ static_assert(sizeof(Anc) == 80, "anchor records are 20 dwords");
 struct TileArgs {
     const unsigned char* proj;   // staged padded projections (or adjoint accumulation buffer)
     const double* coef;          // n_proj x 16 doubles: rows u, v, w of the composed matrix
+                                 // (1/sqrt|s| of the dequantisation factor s folded in), then
+                                 // sign(s) in {+1, -1, 0}
     float* vol;                  // volume buffer (planes z_begin .. z_begin + z_count)
     uint64_t proj_stride;        // bytes between consecutive staged projections
     int32_t n_proj;

@@ -375,9 +375,11 @@ __device__ __forceinline__ void with_walk(const double* c, F&& body)
     else body(std::false_type{});
 }
 
-// The 12 FP64 coefficients of projection k (16 are stored per projection).
+// The 12 FP64 coefficients of projection k and the sign of its
+// dequantisation factor (c[12]: +1, -1 or 0; 16 doubles are stored per
+// projection).
 struct Coef {
-    double c[12];
+    double c[13];
 };
 
 // Coefficients of projection k, read through the scalar cache (the table is
@@ -388,8 +390,18 @@ __device__ __forceinline__ Coef load_coef(const double* tab, int k)
     Coef r;
     DC* t = (DC*)(tab + 16 * k);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) r.c[i] = t[i];
+    for (int i = 0; i < 13; ++i) r.c[i] = t[i];
     return r;
+}
+
+// A projection with a negative dequantisation factor is subtracted: the
+// accumulators are negated before and after its samples are added (a uniform
+// branch, so projections with a positive factor pay nothing).
+template <int S>
+__device__ __forceinline__ void negate_acc(float (&acc)[S])
+{
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = -acc[s];
 }
 
 // Projection order of a tile.  Workgroups start one after another as slots
@@ -439,9 +451,12 @@ __device__ __forceinline__ void bp_tile(const TileArgs& a, int tile, int rot_div
         const unsigned char* img = po.img;
         po.advance(a);
         if (n + 1 < a.n_proj) next = load_coef(a.coef, po.k);
+        if (cur.c[12] == 0.0) continue;   // zero dequantisation factor
         const Strip st = strip_setup<Smp::kShift>(cur.c, p, a, wp);
         if (__builtin_amdgcn_ballot_w64(strip_touches<S>(st)) == 0) continue;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
+        const bool neg = cur.c[12] < 0.0;
+        if (neg) negate_acc(acc);
         with_walk(cur.c, [&](auto cw) {
             const Walk<decltype(cw)::value> wk(st);
 #pragma unroll
@@ -457,6 +472,7 @@ __device__ __forceinline__ void bp_tile(const TileArgs& a, int tile, int rot_div
                 acc[s] = fmaf(val, wgt, acc[s]);
             }
         });
+        if (neg) negate_acc(acc);
     }
     if (p.x < a.L && p.y < a.L) {
         const int64_t plane = (int64_t)a.L * a.L;
@@ -534,7 +550,9 @@ __global__ void window_kernel(TileArgs a, int strip, int bx, int by, Win* __rest
     }
     Win wv;
     // support of a sample, centred coordinates: (-1 - cu, W - cu) = (lo + 1, hi - 1)
-    const bool off = !(ihi > a.lo_x + 0.99 && ilo < a.hi_x - 0.99 && jhi > a.lo_y + 0.99 && jlo < a.hi_y - 0.99);
+    // (a projection whose dequantisation factor is zero adds nothing: empty window)
+    const bool off = !(ihi > a.lo_x + 0.99 && ilo < a.hi_x - 0.99 && jhi > a.lo_y + 0.99 && jlo < a.hi_y - 0.99) ||
+                     c[12] == 0.0;
     if (off || !(ilo == ilo) || !(jlo == jlo)) {
         wv.i0 = 1; wv.i1 = 0; wv.j0 = 1; wv.j1 = 0;
     } else {
@@ -582,6 +600,7 @@ __global__ void window_kernel(TileArgs a, int strip, int bx, int by, Win* __rest
         r.loy = (float)(wv.j0 - ay);
         r.hiy = (float)(wv.j1 - 1 - ay);
         r.base = ((ay - wv.j0) * (c_hi - c_lo + 1) + (ax - c_lo)) * 4;
+        r.neg = c[12] < 0.0 ? 1 : 0;
     }
     anc[t] = r;
 }
@@ -958,11 +977,14 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
                     }
                 }
             };
+            const bool neg = CWM == 2 ? cur.c[12] < 0.0 : an.neg != 0;
+            if (neg) negate_acc(acc);
             if constexpr (CWM == 2) {
                 with_walk(cur.c, sample);
             } else {
                 sample(std::integral_constant<bool, CWM == 1>{});
             }
+            if (neg) negate_acc(acc);
         }
         big |= !wv.fits && !wv.empty;
         wv = wn;
@@ -975,6 +997,8 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
             const LdsWin w(load_win(wins + k), kWave * NW);
             if (w.fits || w.empty) continue;
             const Coef cur = load_coef(a.coef, k);
+            const bool neg = cur.c[12] < 0.0;
+            if (neg) negate_acc(acc);
             const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.proj + (uint64_t)k * a.proj_stride, a.proj_bytes);
             const Strip st = strip_setup<Sampler<T, 0>::kShift>(cur.c, p, a, wp);
             if (RAWOK && raw) {
@@ -994,6 +1018,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
                                              im.H),
                                   r * r, acc[s]);
                 }
+                if (neg) negate_acc(acc);
                 continue;
             }
 #pragma unroll
@@ -1011,6 +1036,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
                 const float val = Sampler<T, 0>::sample(rs, off, row, sx, sy);
                 acc[s] = fmaf(val, r * r, acc[s]);
             }
+            if (neg) negate_acc(acc);
         }
     }
     if (p.x < a.L && p.y < a.L) {

@@ -125,20 +125,27 @@ __global__ __launch_bounds__(256) void stage_batched_kernel(const StageArgs* __r
     }
 }
 
-// out[p][0..11] = coef64[p][0..11] / sqrt(scale_p) in FP64 (16 doubles per
-// projection): folding the dequantisation factor into the matrix scales w by
-// 1/sqrt(s), so the kernel's 1/w^2 weight carries s while u/w and v/w are
-// untouched.
+// Dequantisation factor s of a projection, folded into its coefficients
+// (16 doubles per projection): |s| scales w by 1/sqrt|s|, so the kernel's
+// 1/w^2 weight carries |s| while u/w and v/w are untouched, and slot 12 holds
+// the sign, +1 or -1, or 0 for s = 0 (the projection then adds nothing and is
+// skipped).  Slots 13..15 are zero.
+__device__ __forceinline__ double fold_entry(const double* coef64, int p, int c, const float* sp)
+{
+    const double s = sp != nullptr ? (double)*sp : 1.0;
+    if (c == 12) return s > 0.0 ? 1.0 : s < 0.0 ? -1.0 : 0.0;
+    if (c > 12) return 0.0;
+    const double f = (s > 0.0 || s < 0.0) ? 1.0 / sqrt(fabs(s)) : 1.0;
+    return coef64[p * 12 + c] * f;
+}
+
 __global__ void fold_kernel(const double* __restrict__ coef64, const float* const* __restrict__ scale_ptrs,
                             double* __restrict__ out, int n_total)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_total * 16) return;
     const int p = t >> 4, c = t & 15;
-    if (c >= 12) { out[t] = 0.0; return; }
-    double f = 1.0;
-    if (scale_ptrs != nullptr && scale_ptrs[p] != nullptr) f = 1.0 / sqrt((double)*scale_ptrs[p]);
-    out[t] = coef64[p * 12 + c] * f;
+    out[t] = fold_entry(coef64, p, c, scale_ptrs != nullptr ? scale_ptrs[p] : nullptr);
 }
 
 __global__ void fold_single_kernel(const double* __restrict__ coef64, const float* __restrict__ scale,
@@ -147,9 +154,7 @@ __global__ void fold_single_kernel(const double* __restrict__ coef64, const floa
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * 16) return;
     const int p = t >> 4, c = t & 15;
-    if (c >= 12) { out[t] = 0.0; return; }
-    const double f = scale != nullptr ? 1.0 / sqrt((double)scale[p]) : 1.0;
-    out[t] = coef64[p * 12 + c] * f;
+    out[t] = fold_entry(coef64, p, c, scale != nullptr ? scale + p : nullptr);
 }
 
 __global__ void reset_counter_kernel(unsigned* c) { *c = 0u; }

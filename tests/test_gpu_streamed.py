@@ -143,3 +143,42 @@ def test_streamed_full_size(fdk):
     g = got[torch.from_numpy(xyz[:, 2]), torch.from_numpy(xyz[:, 1]), torch.from_numpy(xyz[:, 0])].cpu().numpy()
     scale = np.abs(ref).max()
     assert np.abs(g - ref).max() <= 1e-4 * scale
+
+
+def test_streamed_waits_for_caller_stream(fdk):
+    """A device stack written on the caller's stream just before the call
+    (packed there, no host synchronisation in between) is gathered only after
+    it is written: the library's copy stream waits for the caller's."""
+    mats, proj = _case(tilt=1.0, seed=12)
+    L, voxel = 30, 4.0
+    geom, vol = fdk.Geometry(mats, 96, 48), fdk.Volume(L, voxel)
+    ref = oracle.backproject(L, voxel, mats, proj.numpy())
+    src = proj.to(DEV)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        # a long queue of work ahead of the pack keeps it from finishing early
+        junk = torch.randn((2048, 2048), device=DEV)
+        for _ in range(20):
+            junk = junk @ junk
+            junk = junk / junk.abs().max()
+        stack = src * 2.0
+        got = fdk.backproject_streamed(stack, geom, vol, 4, stream=side)
+        got2 = fdk.backproject_streamed(stack * 0.5, geom, vol, 7, stream=side)
+    side.synchronize()
+    assert_parity(got.cpu().numpy(), 2.0 * ref, what="streamed after pack on a side stream")
+    assert_parity(got2.cpu().numpy(), ref, what="second call, other slabs")
+
+
+def test_streamed_many_slabs_repeat(fdk):
+    """More slabs than there are cached geometries: repeated calls reuse the
+    one table composed for all slabs of a call."""
+    mats, proj = _case(seed=13)
+    L, voxel = 40, 3.2
+    geom, vol = fdk.Geometry(mats, 96, 48), fdk.Volume(L, voxel)
+    ref = oracle.backproject(L, voxel, mats, proj.numpy())
+    host = proj.pin_memory()
+    for _ in range(3):
+        got = fdk.backproject_streamed(host, geom, vol, 1)   # 40 slabs
+        torch.cuda.synchronize()
+        assert_parity(got.cpu().numpy(), ref, what="40 one-plane slabs")
