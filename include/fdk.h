@@ -143,6 +143,30 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj,
                            float* volume, int accumulate, void* stream);
 
 /*
+ * fdk_backproject for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result, computed without any allocation.  Its working memory (the
+ * coefficient tables and the LDS window table of one z-chunk) is a 32 MiB
+ * array in the library's device code, one copy per device, held until the
+ * process ends; the call allocates nothing, neither on the device nor through
+ * a library.  FP32 projections only, read in place.
+ *   vol, proj, volume, accumulate, stream  as for fdk_backproject
+ * Limits (FDK_E_INVALID_ARG beyond them, nothing enqueued): n_proj <= 4096;
+ * ceil(L/16)^2 * n_proj * 8 bytes <= 31 MiB (one window table entry per
+ * 16x16x16 tile and projection, for 16 planes: L = 512 allows 4000
+ * projections); width * height * 4 < 4 GiB.  FDK_E_UNSUPPORTED for FP16/BF16
+ * data.  The matrices are copied from the host by the call (from pageable
+ * memory, so the host may wait for the stream).  Every call on one device
+ * shares that device's array and leaves its contents behind; the library
+ * orders its own calls (a call on a new stream first waits for the previous
+ * call's work), and calls made around that ordering, e.g. from two processes
+ * sharing the library's code object or work captured into graphs that are
+ * replayed concurrently, would race on it.
+ */
+fdk_status fdk_backproject_noalloc(const fdk_volume* vol, const fdk_projections* proj, float* volume,
+                                   int accumulate, void* stream);
+
+/*
  * Voxel-driven forward projection, the exact adjoint B^T of fdk_backproject
  * (the transpose of the linear map of Listing 1): for every voxel v and
  * projection k the value volume[v] / w^2 is scattered onto the four bilinear

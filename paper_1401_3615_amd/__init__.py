@@ -22,6 +22,7 @@ from . import _build
 
 __all__ = [
     "FdkError", "Volume", "Geometry", "F32", "F16", "BF16", "TUNE_ADJOINT", "TUNE_BATCHED", "load", "backproject",
+    "backproject_noalloc",
     "forwardproject", "backproject_batched", "pack_projections", "set_tile", "get_tile",
     "load_tuning", "set_tuning_entry", "validate", "release_workspace", "abi_version",
     "BackProject", "ForwardProject", "Scan", "profile_enable", "profile_read", "FilterGeometry",
@@ -72,6 +73,7 @@ def load():
     pv, pp, ps = ctypes.POINTER(_Volume), ctypes.POINTER(_Proj), ctypes.POINTER(_Scan)
     sig = {
         "fdk_backproject": ([pv, pp, vp, ctypes.c_int, vp], ctypes.c_int),
+        "fdk_backproject_noalloc": ([pv, pp, vp, ctypes.c_int, vp], ctypes.c_int),
         "fdk_forwardproject": ([pv, vp, pp, vp, ctypes.c_int, vp], ctypes.c_int),
         "fdk_backproject_batched": ([ps, i32, ctypes.c_int, vp], ctypes.c_int),
         "fdk_pack_projections": ([vp, i32, i32, i32, i32, vp, vp, vp], ctypes.c_int),
@@ -213,6 +215,31 @@ def backproject(proj: torch.Tensor, geom: Geometry, vol: Volume, out: torch.Tens
     _check(lib.fdk_backproject(ctypes.byref(v), ctypes.byref(p),
                                _dev_ptr(out, "volume", (torch.float32,)), int(bool(accumulate)),
                                _stream(stream)))
+    return out
+
+
+def backproject_noalloc(proj: torch.Tensor, geom: Geometry, vol: Volume, out: torch.Tensor,
+                        accumulate: bool = False, scale: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """fdk_backproject_noalloc: fdk_backproject without any device allocation
+    (FP32 projections; the caller provides `out`)."""
+    lib = load()
+    if proj.dtype not in _TORCH_DTYPE:
+        raise FdkError(-3, f"projection dtype {proj.dtype}")
+    if tuple(proj.shape) != (geom.n_proj, geom.height, geom.width):
+        raise FdkError(-1, f"projections {tuple(proj.shape)} do not match geometry "
+                           f"{(geom.n_proj, geom.height, geom.width)}")
+    if tuple(out.shape) != (vol.planes, vol.L, vol.L) or out.dtype != torch.float32:
+        raise FdkError(-1, "output volume has the wrong shape or dtype")
+    sp = None
+    if scale is not None:
+        if scale.numel() != geom.n_proj:
+            raise FdkError(-1, "scale must have one entry per projection")
+        sp = _dev_ptr(scale, "scale", (torch.float32,))
+    v = vol.c()
+    p = geom.c(_dev_ptr(proj, "projections"), _TORCH_DTYPE[proj.dtype], sp)
+    _check(lib.fdk_backproject_noalloc(ctypes.byref(v), ctypes.byref(p),
+                                       _dev_ptr(out, "volume", (torch.float32,)), int(bool(accumulate)),
+                                       _stream(stream)))
     return out
 
 

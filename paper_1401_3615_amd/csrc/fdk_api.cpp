@@ -130,11 +130,10 @@ struct Composed {
     bool const_w;              // w independent of z for every projection (coefficient exactly 0)
 };
 
-Composed compose(const fdk_volume* v, const fdk_projections* p)
+// Writes n_proj * 12 doubles to `coef` (no allocation).
+void compose_into(const fdk_volume* v, const fdk_projections* p, double* coef, float* out_scale, bool* const_w)
 {
-    Composed c;
     const int N = p->n_proj;
-    c.coef.resize((size_t)N * 12);
     const int ctr = v->L / 2;
     const double cu = (double)(p->width / 2), cv = (double)(p->height / 2);
     double wsum = 0.0;
@@ -154,16 +153,24 @@ Composed compose(const fdk_volume* v, const fdk_projections* p)
             M[1][a] -= cv * M[2][a];
         }
         for (int r = 0; r < 3; ++r)
-            for (int a = 0; a < 4; ++a) c.coef[(size_t)k * 12 + r * 4 + a] = M[r][a];
+            for (int a = 0; a < 4; ++a) coef[(size_t)k * 12 + r * 4 + a] = M[r][a];
         wsum += std::fabs(M[2][3]);
     }
     const double wmean = wsum / N;
     const int e = (wmean > 0.0 && std::isfinite(wmean)) ? -(int)std::lround(std::log2(wmean)) : 0;
     const double s = std::ldexp(1.0, e);
-    for (double& x : c.coef) x *= s;
-    c.out_scale = (float)std::ldexp(1.0, 2 * e);
-    c.const_w = true;
-    for (int k = 0; k < N; ++k) c.const_w = c.const_w && c.coef[(size_t)k * 12 + 10] == 0.0;
+    for (size_t i = 0; i < (size_t)N * 12; ++i) coef[i] *= s;
+    *out_scale = (float)std::ldexp(1.0, 2 * e);
+    bool cw = true;
+    for (int k = 0; k < N; ++k) cw = cw && coef[(size_t)k * 12 + 10] == 0.0;
+    *const_w = cw;
+}
+
+Composed compose(const fdk_volume* v, const fdk_projections* p)
+{
+    Composed c;
+    c.coef.resize((size_t)p->n_proj * 12);
+    compose_into(v, p, c.coef.data(), &c.out_scale, &c.const_w);
     return c;
 }
 
@@ -387,6 +394,7 @@ struct FilterEntry {
 struct DeviceState {
     bool init = false;
     bool arch_ok = false;
+    unsigned char* scratch = nullptr;   // this device's copy of the allocation-free scratch array
     int num_cus = 0;
     std::string arch;
     DevBuf staged, coef_dev, adjoint, windows;
@@ -416,6 +424,20 @@ struct DeviceState {
     bool band_used[2] = {false, false}, slab_used[2] = {false, false};
 };
 
+// Scratch memory of fdk_backproject_noalloc, one copy per device, held until
+// the process ends: the folded coefficient table, the composed one, and the
+// window table of one z-chunk.  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (DeviceState::scratch).
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kNoAllocMaxProj = 4096;
+constexpr size_t kScratchFolded = 0;                                         // n_proj x 16 doubles
+constexpr size_t kScratchComposed = (size_t)kNoAllocMaxProj * 16 * 8;        // n_proj x 12 doubles
+constexpr size_t kScratchWin = kScratchComposed + (size_t)kNoAllocMaxProj * 12 * 8;   // windows
+static_assert(kScratchWin % 256 == 0, "window table offset");
+static __device__ __align__(256) unsigned char g_scratch[kScratchBytes];
+// host source of the coefficient upload (guarded by g_mu)
+double g_noalloc_coef[kNoAllocMaxProj * 12];
+
 // Recursive: the iterative solvers call the projector entry points while holding it.
 std::recursive_mutex g_mu;
 std::map<int, DeviceState> g_dev;
@@ -436,6 +458,15 @@ fdk_status device_state(DeviceState** out)
         d.arch_ok = d.arch.rfind("gfx950", 0) == 0;
         d.num_cus = prop.multiProcessorCount;
         HIP_TRY(hipEventCreateWithFlags(&d.done, hipEventDisableTiming));
+        if (d.arch_ok) {
+            // the device address of this device's copy of the scratch array (the
+            // array's name in host code is only a stand-in for the symbol)
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_scratch));
+            if (e != hipSuccess)
+                return fail(FDK_E_DEVICE, "scratch array of device %d: %s", dev, hipGetErrorString(e));
+            d.scratch = static_cast<unsigned char*>(p);
+        }
         d.init = true;
     }
     if (!d.arch_ok)
@@ -827,6 +858,73 @@ fdk_status fdk_backproject(const fdk_volume* vol, const fdk_projections* proj, f
     std::lock_guard<std::recursive_mutex> lock(g_mu);
     load_env_tuning();
     return backproject_impl(vol, proj, volume, accumulate, static_cast<hipStream_t>(stream), nullptr, nullptr);
+}
+
+fdk_status fdk_backproject_noalloc(const fdk_volume* vol, const fdk_projections* proj, float* volume,
+                                   int accumulate, void* stream)
+{
+    fdk_status st = fdk_validate(vol, proj, 1);
+    if (st != FDK_OK) return st;
+    if (volume == nullptr) return fail(FDK_E_INVALID_ARG, "volume buffer is NULL");
+    if (proj->dtype != FDK_F32)
+        return fail(FDK_E_UNSUPPORTED, "the allocation-free backprojection reads FP32 projections only");
+    if (proj->n_proj > kNoAllocMaxProj)
+        return fail(FDK_E_INVALID_ARG, "n_proj=%d exceeds the allocation-free maximum of %d", proj->n_proj,
+                    kNoAllocMaxProj);
+    if ((uint64_t)proj->width * proj->height * 4 > 0xffffffffull)
+        return fail(FDK_E_INVALID_ARG, "projection of %dx%d pixels exceeds 4 GiB", proj->width, proj->height);
+    // one tile shape: 16 x 16 columns, 16 planes deep; z-chunks of whole tile
+    // layers whose window tables fit the scratch
+    constexpr int kStrip = 16, kWaves = 4, kSide = 16;
+    const uint64_t tiles_xy = (uint64_t)((vol->L + kSide - 1) / kSide) * ((vol->L + kSide - 1) / kSide);
+    const uint64_t layer_bytes = tiles_xy * (uint64_t)proj->n_proj * sizeof(Win);
+    const uint64_t budget = kScratchBytes - kScratchWin;
+    if (layer_bytes > budget)
+        return fail(FDK_E_INVALID_ARG,
+                    "grid of %d^2 columns x %d projections needs %llu bytes of window table per 16 planes; the "
+                    "allocation-free scratch holds %llu", vol->L, proj->n_proj, (unsigned long long)layer_bytes,
+                    (unsigned long long)budget);
+    const int chunk_planes = (int)std::min<uint64_t>(budget / layer_bytes, 1u << 20) * kStrip;
+    std::lock_guard<std::recursive_mutex> lock(g_mu);
+    DeviceState* d = nullptr;
+    if ((st = device_state(&d)) != FDK_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = begin_call(*d, s)) != FDK_OK) return st;
+    float out_scale = 1.0f;
+    bool const_w = false;
+    compose_into(vol, proj, g_noalloc_coef, &out_scale, &const_w);
+    for (int i = 0; i < proj->n_proj * 12; ++i)
+        if (!std::isfinite((float)g_noalloc_coef[i]))
+            return fail(FDK_E_INVALID_ARG, "composed projection matrix exceeds FP32 range");
+    double* folded = reinterpret_cast<double*>(d->scratch + kScratchFolded);
+    double* composed = reinterpret_cast<double*>(d->scratch + kScratchComposed);
+    Win* win = reinterpret_cast<Win*>(d->scratch + kScratchWin);
+    // from pageable memory: the runtime has read the source when the call returns
+    HIP_TRY(hipMemcpyAsync(composed, g_noalloc_coef, (size_t)proj->n_proj * 12 * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fold_single(composed, proj->scale, folded, proj->n_proj, s));
+    const TileShape t{kStrip, kWaves, 3};
+    const size_t plane = (size_t)vol->L * vol->L;
+    for (int z0 = 0; z0 < vol->z_count; z0 += chunk_planes) {
+        fdk_volume cv = *vol;
+        cv.z_begin = vol->z_begin + z0;
+        cv.z_count = std::min(chunk_planes, vol->z_count - z0);
+        TileArgs a = make_args(&cv, proj, 4, t, nullptr, folded, volume + (size_t)z0 * plane, out_scale, accumulate,
+                               FDK_F32);
+        // the caller's unpadded images, row pitch W, sampled through LDS windows
+        const uint64_t img = (uint64_t)proj->width * proj->height * 4;
+        a.proj = static_cast<const unsigned char*>(proj->data);
+        a.proj_stride = img;
+        a.proj_bytes = (uint32_t)img;
+        a.row_bytes = (uint32_t)proj->width * 4;
+        a.raw = 1;
+        a.const_w = const_w ? 1 : 0;
+        a.win = win;
+        a.anc = nullptr;
+        HIP_TRY(launch_window(a, kStrip, kWaves, win, nullptr, s));
+        HIP_TRY(launch_bp_lanes(a, s));
+    }
+    return end_call(*d, s);
 }
 
 // Forward projection by detector-tile ownership: each workgroup owns t.strip

@@ -151,6 +151,10 @@ hipError_t launch_fold(const double* coef64, const float* const* scale_ptrs, dou
 hipError_t launch_fold_single(const double* coef64, const float* scale, double* out, int n,
                               hipStream_t s);
 hipError_t launch_bp(const TileArgs& a, int strip, int waves, hipStream_t s);
+// The LDS backprojection of the caller's unpadded FP32 images with per-lane
+// anchors (no sampling set-up table), tile 16 planes x 4 waves; a.win holds
+// the windows of that tile shape.
+hipError_t launch_bp_lanes(const TileArgs& a, hipStream_t s);
 hipError_t launch_fp(const TileArgs& a, int strip, int waves, hipStream_t s);
 hipError_t launch_bp_batched(const TileArgs* dev_scans, const int32_t* dev_item_begin, int n_scans,
                              unsigned* dev_counter, int total_items, int grid, int strip, int waves,

@@ -1497,6 +1497,12 @@ hipError_t launch_bp(const TileArgs& a, int strip, int waves, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_bp_lanes(const TileArgs& a, hipStream_t s)
+{
+    launch_rotated(bp_lds_kernel<float, 16, 4, 2, true>, a, dim3(tile_blocks(a)), dim3(kWave * 4), s);
+    return hipGetLastError();
+}
+
 hipError_t launch_fp(const TileArgs& a, int strip, int waves, hipStream_t s)
 {
     const int nb = tile_blocks(a);

@@ -373,3 +373,24 @@ def test_solver_history_must_be_device_memory(fdk):
     assert lib.fdk_cgls(ctypes.byref(v), ctypes.byref(p), 1, 2, 0, host.ctypes.data, None) == -1
     assert b"history" in lib.fdk_last_error()
     assert lib.fdk_sirt(ctypes.byref(v), ctypes.byref(p), 1, 2, 1.0, 0, host.ctypes.data, None) == -1
+
+
+def test_noalloc_limits_checked_on_host(fdk):
+    """fdk_backproject_noalloc rejects FP16 data, more than 4096 projections
+    and grids whose window table exceeds its scratch array, on the host,
+    before any device access (the device pointers here are never touched)."""
+    lib = fdk.load()
+    fake = ctypes.c_void_p(0x1000)
+
+    def call(L, N, dtype=0, W=32, H=24):
+        mats = S.tiny_cone_matrices(N, W, H, L, 16.0 / L, 0)
+        g, v = fdk.Geometry(mats, W, H), fdk.Volume(L, 16.0 / L)
+        p = g.c(fake, dtype, None)
+        return lib.fdk_backproject_noalloc(ctypes.byref(v.c()), ctypes.byref(p), fake, 0, None)
+
+    assert call(16, 4, dtype=1) == -3
+    assert call(16, 4097) == -1
+    assert b"4096" in lib.fdk_last_error()
+    # ceil(2048 / 16)^2 * 300 * 8 bytes = 39.3 MB per 16 planes > 31 MiB
+    assert call(2048, 300) == -1
+    assert b"window table" in lib.fdk_last_error()
