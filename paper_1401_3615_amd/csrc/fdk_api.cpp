@@ -127,11 +127,12 @@ fdk_status check_geometry(const fdk_volume* v, const fdk_projections* p)
 struct Composed {
     std::vector<double> coef;  // n_proj * 12
     float out_scale;
-    bool const_w;              // w independent of z for every projection (coefficient exactly 0)
+    int const_w;               // 1: w independent of z for every projection (coefficient exactly 0),
+                               // 2: u and w both (a circular orbit about the z axis)
 };
 
 // Writes n_proj * 12 doubles to `coef` (no allocation).
-void compose_into(const fdk_volume* v, const fdk_projections* p, double* coef, float* out_scale, bool* const_w)
+void compose_into(const fdk_volume* v, const fdk_projections* p, double* coef, float* out_scale, int* const_w)
 {
     const int N = p->n_proj;
     const int ctr = v->L / 2;
@@ -161,9 +162,12 @@ void compose_into(const fdk_volume* v, const fdk_projections* p, double* coef, f
     const double s = std::ldexp(1.0, e);
     for (size_t i = 0; i < (size_t)N * 12; ++i) coef[i] *= s;
     *out_scale = (float)std::ldexp(1.0, 2 * e);
-    bool cw = true;
-    for (int k = 0; k < N; ++k) cw = cw && coef[(size_t)k * 12 + 10] == 0.0;
-    *const_w = cw;
+    bool cw = true, cz = true;
+    for (int k = 0; k < N; ++k) {
+        cw = cw && coef[(size_t)k * 12 + 10] == 0.0;
+        cz = cz && coef[(size_t)k * 12 + 2] == 0.0;
+    }
+    *const_w = cw ? (cz ? 2 : 1) : 0;
 }
 
 Composed compose(const fdk_volume* v, const fdk_projections* p)
@@ -554,7 +558,7 @@ fdk_status coef_lookup(DeviceState& d, const std::string& key, hipStream_t s,
     for (size_t i = 0; i < cs.size(); ++i) {
         std::copy(cs[i].coef.begin(), cs[i].coef.end(), h + i * per);
         e.out_scale.push_back(cs[i].out_scale);
-        e.const_w.push_back(cs[i].const_w ? 1 : 0);
+        e.const_w.push_back(cs[i].const_w);
     }
     err = hipMemcpyAsync(e.buf.p, e.host.p, bytes, hipMemcpyHostToDevice, s);
     // until the table has been read, recycling this entry must wait for the upload
@@ -891,7 +895,7 @@ fdk_status fdk_backproject_noalloc(const fdk_volume* vol, const fdk_projections*
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = begin_call(*d, s)) != FDK_OK) return st;
     float out_scale = 1.0f;
-    bool const_w = false;
+    int const_w = 0;
     compose_into(vol, proj, g_noalloc_coef, &out_scale, &const_w);
     for (int i = 0; i < proj->n_proj * 12; ++i)
         if (!std::isfinite((float)g_noalloc_coef[i]))
@@ -918,7 +922,7 @@ fdk_status fdk_backproject_noalloc(const fdk_volume* vol, const fdk_projections*
         a.proj_bytes = (uint32_t)img;
         a.row_bytes = (uint32_t)proj->width * 4;
         a.raw = 1;
-        a.const_w = const_w ? 1 : 0;
+        a.const_w = const_w;
         a.win = win;
         a.anc = nullptr;
         HIP_TRY(launch_window(a, kStrip, kWaves, win, nullptr, s));

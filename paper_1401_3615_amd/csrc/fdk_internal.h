@@ -74,7 +74,8 @@ struct TileArgs {
     const Anc* anc;              // layout 3: n_tiles x n_proj sampling set-ups (order of win)
     int32_t cu, cv;              // integer detector centre (W/2, H/2)
     int32_t rot_div;             // projection-order rotation divisor (0: every tile starts at k = 0)
-    int32_t const_w;             // 1: w does not depend on z for any projection of the launch
+    int32_t const_w;             // 1: w does not depend on z for any projection of the launch,
+                                 // 2: neither u nor w does
     int32_t raw;                 // 1: proj holds the caller's FP32 images unpadded (row pitch W,
                                  //    W even; LDS layout only), windows read with bounds checks
 };

@@ -67,6 +67,23 @@ __device__ __forceinline__ uint32_t tap_offset(int i0, int j0, int wp, int base)
     return (uint32_t)off;
 }
 
+// Byte offset of column i0 relative to an anchor: (i0 << 2) + base.
+__device__ __forceinline__ int col_offset(int i0, int base)
+{
+    int off;
+    asm("v_lshl_add_u32 %0, %1, 2, %2" : "=v"(off) : "v"(i0), "v"(base));
+    return off;
+}
+
+// Byte offset of row j0 in rows ROWB bytes apart: j0 * ROWB + col, one VALU op.
+template <int ROWB>
+__device__ __forceinline__ uint32_t row_offset(int j0, int col)
+{
+    int off;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(off) : "v"(j0), "s"(ROWB), "v"(col));
+    return (uint32_t)off;
+}
+
 // One detector row of the 2x2 tap block: the taps (i0, i0+1) come from one
 // load at byte offset `off` (+ `soff`), and row() returns their linear
 // interpolation  l + sx (r - l)  in FP32.
@@ -330,7 +347,8 @@ __device__ __forceinline__ bool strip_touches(const Strip& st)
 template <bool CONSTW>
 struct Walk {
     float ax, bx, ay, by, aw, bw, r2;
-    __device__ __forceinline__ explicit Walk(const Strip& st)
+    // sgn: +1 or -1, the sign of the weight where it is one per strip (CONSTW)
+    __device__ __forceinline__ explicit Walk(const Strip& st, float sgn = 1.0f)
     {
         if (CONSTW) {
             const float r = __builtin_amdgcn_rcpf(st.wb);
@@ -338,7 +356,7 @@ struct Walk {
             bx = st.du * r;
             ay = st.vb * r;
             by = st.dv * r;
-            r2 = r * r;
+            r2 = r * r * sgn;
             aw = bw = 0.0f;
         } else {
             ax = st.ub;
@@ -394,14 +412,16 @@ __device__ __forceinline__ Coef load_coef(const double* tab, int k)
     return r;
 }
 
-// A projection with a negative dequantisation factor is subtracted: the
-// accumulators are negated before and after its samples are added (a uniform
-// branch, so projections with a positive factor pay nothing).
+// A projection with a negative dequantisation factor is subtracted.  Where
+// the weight is one value per strip (w constant along z) its sign is folded
+// into that weight; elsewhere the accumulators are negated before and after
+// the projection's samples are added, under a uniform branch (volatile, so
+// the compiler cannot turn it into sign flips executed for every projection).
 template <int S>
 __device__ __forceinline__ void negate_acc(float (&acc)[S])
 {
 #pragma unroll
-    for (int s = 0; s < S; ++s) acc[s] = -acc[s];
+    for (int s = 0; s < S; ++s) asm volatile("v_xor_b32 %0, 0x80000000, %0" : "+v"(acc[s]));
 }
 
 // Projection order of a tile.  Workgroups start one after another as slots
@@ -456,9 +476,10 @@ __device__ __forceinline__ void bp_tile(const TileArgs& a, int tile, int rot_div
         if (__builtin_amdgcn_ballot_w64(strip_touches<S>(st)) == 0) continue;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
         const bool neg = cur.c[12] < 0.0;
-        if (neg) negate_acc(acc);
         with_walk(cur.c, [&](auto cw) {
-            const Walk<decltype(cw)::value> wk(st);
+            constexpr bool CW = decltype(cw)::value;
+            if (!CW && neg) negate_acc(acc);
+            const Walk<CW> wk(st, neg ? -1.0f : 1.0f);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 constexpr int kMid = S / 2;
@@ -471,8 +492,8 @@ __device__ __forceinline__ void bp_tile(const TileArgs& a, int tile, int rot_div
                 const float val = Smp::sample(rs, off, row, sx, sy);
                 acc[s] = fmaf(val, wgt, acc[s]);
             }
+            if (!CW && neg) negate_acc(acc);
         });
-        if (neg) negate_acc(acc);
     }
     if (p.x < a.L && p.y < a.L) {
         const int64_t plane = (int64_t)a.L * a.L;
@@ -524,7 +545,8 @@ __global__ __launch_bounds__(kWave * NW)
 // the hull of its corners), widened by one pixel against FP32 rounding in the
 // kernel.  A tile whose footprint misses the detector gets an empty window:
 // the paper's clipping mask at tile granularity.
-__global__ void window_kernel(TileArgs a, int strip, int bx, int by, Win* __restrict__ out, Anc* __restrict__ anc)
+__global__ void window_kernel(TileArgs a, int strip, int bx, int by, int pitch, Win* __restrict__ out,
+                              Anc* __restrict__ anc)
 {
     const int64_t n_tiles = (int64_t)a.tiles_x * a.tiles_y * a.tiles_z;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -599,7 +621,7 @@ __global__ void window_kernel(TileArgs a, int strip, int bx, int by, Win* __rest
         r.hix = (float)(c_hi - 1 - ax);
         r.loy = (float)(wv.j0 - ay);
         r.hiy = (float)(wv.j1 - 1 - ay);
-        r.base = ((ay - wv.j0) * (c_hi - c_lo + 1) + (ax - c_lo)) * 4;
+        r.base = ((ay - wv.j0) * pitch + (ax - c_lo)) * 4;
         r.neg = c[12] < 0.0 ? 1 : 0;
     }
     anc[t] = r;
@@ -654,30 +676,65 @@ template <> struct Chunk<bf16_t> {
     }
 };
 
-constexpr int kLdsCap = 8192;   // FP32 pixels of the per-workgroup projection tile (32 KiB)
-
 // Backprojection with the projection footprint of the workgroup staged in
 // LDS: per projection the tile's window is copied from the staged image with
 // aligned 16-byte loads (all threads), and the four taps of every voxel are
 // then read from LDS, which keeps the scattered gathers off the vector-memory
-// path.  A window larger than the LDS tile falls back to gathers from the
-// staged image for that projection.
-// Occupancy of the LDS kernel: five 32 KiB tiles fit in the 160 KiB of a CU.
-template <int S, int NW>
+// path.
+//
+// The LDS window of a workgroup has rows of a fixed pitch (a compile-time
+// constant, so the second tap row of a sample is an immediate offset of the
+// same LDS read) and at most lds_rows<S>() rows.  Both are sized for the
+// footprints of the target geometry: 0.5 mm voxels seen at up to 2.1x
+// magnification on a 0.308 mm detector, i.e. up to 80 x 63 pixels for a
+// 16 x 16 x 16 tile (16, 36 and 116 rows for 4, 8 and 32 planes; 44 pixels
+// wide for 8-column tiles).  A larger window is gathered from the staged
+// image instead.  The caps, not the largest possible window, set how many
+// workgroups share a CU: for the 16 x 16 x 16 tile, 21 KiB each, seven fit in
+// its 160 KiB (registers then allow six).  Rows 84 floats apart put
+// vertically adjacent taps 20 banks apart.
+template <int NW> constexpr int lds_pitch() { return NW == 1 ? 52 : 84; }
+template <int S> constexpr int lds_rows() { return S >= 32 ? 120 : S >= 16 ? 64 : S >= 8 ? 40 : S >= 4 ? 24 : 16; }
+template <int S, int NW> constexpr int lds_cap() { return lds_rows<S>() * lds_pitch<NW>(); }
+
+// Occupancy of the LDS kernels: the workgroups whose windows fit a CU's
+// 160 KiB, as waves per SIMD, capped by what the tile body's registers allow
+// without spilling (from the compiled register counts): the column walk
+// (CWM 3) over a staged image needs the fewest, the per-voxel walks, the
+// bounds-checked fills of unpadded images (RAWOK) and the per-lane anchors
+// (CWM 2) more; 16-bit windows hold half the prefetched bits.
+template <int S, int NW, int CWM, bool RAWOK, bool HALF>
+constexpr int lds_vgpr_waves()
+{
+    if (S <= 4) return CWM == 2 || NW < 4 ? 6 : 8;
+    if (CWM == 2) return S <= 8 ? 4 : 3;
+    const bool lean = CWM == 3 && !RAWOK;
+    if (S <= 8) return lean ? 7 : 5;
+    if (S <= 16) return lean ? 6 : (HALF || (CWM == 1 && !RAWOK)) ? 5 : 4;
+    return lean || HALF ? 4 : 3;
+}
+template <int S, int NW, int CWM, bool RAWOK, bool HALF>
 constexpr int lds_waves_per_eu()
 {
-    // five 32 KiB tiles per CU; strips of 32 keep more accumulators and fit three
-    return (5 * NW / 4) < 1 ? 1 : ((5 * NW / 4) < (S <= 16 ? 5 : 3) ? (5 * NW / 4) : (S <= 16 ? 5 : 3));
+    constexpr int per_cu = (160 * 1024) / (lds_cap<S, NW>() * 4);
+    constexpr int w = per_cu * NW / 4;
+    constexpr int v = lds_vgpr_waves<S, NW, CWM, RAWOK, HALF>();
+    return w < 1 ? 1 : (w < v ? w : v);
 }
 
+// The persistent batched kernel holds every sampling path (gathers from the
+// three staged layouts, LDS windows of the three dtypes): its own budget.
+template <int S> constexpr int batched_waves_per_eu() { return S <= 2 ? 5 : S <= 8 ? 4 : 3; }
+
 // The window of one projection as the LDS tile holds it: 4-pixel chunks
-// [c_lo, c_hi] x [j0, j1] of the staged image, row pitch tw pixels.  It fits
-// when it holds at most kLdsCap pixels in rows of at most NT chunks (NT =
-// threads of the workgroup, which copy a row's chunks side by side).
+// [c_lo, c_hi] x [j0, j1] of the staged image, in rows `pitch` pixels apart.
+// It fits when its rows are at most `pitch` pixels and at most cap / pitch
+// rows (every row's chunks are copied side by side by the workgroup's
+// threads, of which there are more than chunks in a row).
 struct LdsWin {
     int c_lo, c_hi, j0, j1, tw, th, nc, total;   // total = chunks = nc * th
     bool empty, fits;
-    __device__ __forceinline__ LdsWin(Win w, int max_nc)
+    __device__ __forceinline__ LdsWin(Win w, int pitch, int cap)
     {
         empty = w.i0 > w.i1;
         c_lo = w.i0 & ~3;
@@ -688,23 +745,30 @@ struct LdsWin {
         th = j1 - j0 + 1;
         nc = tw >> 2;
         total = empty ? 0 : nc * th;
-        fits = !empty && tw * th <= kLdsCap && nc <= max_nc;
+        fits = !empty && tw <= pitch && th * pitch <= cap;
     }
 };
 
-// Chunks of a window prefetched into registers per thread while the previous
-// projection is sampled (up to kPre x 256 threads x 4 pixels = 4096 pixels for
-// a 4-wave workgroup), with the LDS offset each one goes to; larger windows
-// load their remainder after the barrier.
-constexpr int kPre = 4;
+// How the threads of a workgroup copy a window: a row of the LDS window has
+// kCols = pitch / 4 chunk slots, and thread t always takes slot t mod kCols
+// of rows r0 = t / kCols, r0 + kRows, r0 + 2 kRows, ... (kRows = threads /
+// kCols rows per pass; the threads past kRows * kCols copy nothing, as do the
+// slots past the window's own width).  The split is fixed per thread, so the
+// only per-projection set-up is the first chunk's source pixel.  The first
+// kPre chunks of a thread are prefetched into registers while the previous
+// projection is sampled; rows past them are loaded after the barrier.
+constexpr int kPre = 5;
+
+template <int NW> struct FillSplit {
+    static constexpr int kCols = lds_pitch<NW>() / 4;
+    static constexpr int kRows = kWave * NW / kCols;
+};
 
 template <typename T>
 struct Fill {
-    typename Chunk<T>::Raw v[kPre];   // chunk i: row r0 + i * R of this thread's chunk column
-    int r0, lo0;      // first row and its LDS float offset (r0 >= th: none)
-    uint32_t px0;     // first chunk's source pixel
-    int R, dlo;       // rows per pass and the LDS step per pass (uniform)
-    uint32_t dpx;     // source step per pass (uniform)
+    typename Chunk<T>::Raw v[kPre];   // chunk i: row r0 + i * kRows of this thread's slot
+    uint32_t px0;                     // first chunk's source pixel
+    bool on;                          // the slot lies inside the window
 };
 
 // Unpadded source images (RAW): window pixel (ip, jp) is image pixel
@@ -750,53 +814,45 @@ __device__ __forceinline__ typename Chunk<T>::Raw window_chunk(__amdgpu_buffer_r
     return Chunk<T>::load(rs, px);
 }
 
-// How the threads of a workgroup split a window: thread t copies chunk column
-// cc = t mod nc of rows r0 = t / nc, r0 + R, r0 + 2R, ... with R = NT / nc >= 1
-// rows per pass (a fitting window has nc <= NT; the threads from R * nc on
-// copy nothing), so that from one chunk to the next the source and LDS
-// offsets advance by uniform steps.
 template <typename T, int NW, bool RAWOK = false>
 __device__ __forceinline__ void window_prefetch(Fill<T>& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs, int wp,
-                                                const RawImg& im = RawImg{0, 0}, bool raw = false)
+                                                int r0, int cc, const RawImg& im = RawImg{0, 0}, bool raw = false)
 {
-    constexpr int NT = kWave * NW;
+    using FS = FillSplit<NW>;
     const bool edge = RAWOK && raw && raw_edge(w, im);
-    // (e + 0.5) * rcp(nc) floors to e / nc exactly: the relative error of the
-    // product (2 ulp) stays below 0.5 / nc for e, nc < 2^14
-    const float inv_nc = __builtin_amdgcn_rcpf((float)w.nc);
-    f.R = __builtin_amdgcn_readfirstlane((int)(((float)NT + 0.5f) * inv_nc));
-    const int t = (int)threadIdx.x;
-    int r0 = (int)(((float)t + 0.5f) * inv_nc);
-    const int cc = t - __mul24(r0, w.nc);
-    if (r0 >= f.R) r0 = w.th;   // idle thread: its rows start past the window
     const int sh = RAWOK && raw ? kPadLo : 0;
-    f.r0 = r0;
+    f.on = cc < w.nc;
     f.px0 = (uint32_t)(__mul24(w.j0 + r0 - sh, wp) + w.c_lo - sh + 4 * cc);
-    f.lo0 = __mul24(r0, w.tw) + 4 * cc;
-    // uniform steps, kept opaque so that each chunk's offsets are one add
-    f.dpx = (uint32_t)__builtin_amdgcn_readfirstlane(__mul24(f.R, wp));
-    f.dlo = __builtin_amdgcn_readfirstlane(__mul24(f.R, w.tw));
+    // uniform step, kept opaque so that each chunk's offset is one add
+    const uint32_t dpx = (uint32_t)__builtin_amdgcn_readfirstlane(__mul24(FS::kRows, wp));
 #pragma unroll
     for (int i = 0; i < kPre; ++i)
-        if (r0 + i * f.R < w.th)
-            f.v[i] = window_chunk<T, RAWOK>(rs, w, wp, r0 + i * f.R, cc, f.px0 + (uint32_t)i * f.dpx, im, raw, edge);
+        if (f.on && r0 + i * FS::kRows < w.th)
+            f.v[i] = window_chunk<T, RAWOK>(rs, w, wp, r0 + i * FS::kRows, cc, f.px0 + (uint32_t)i * dpx, im, raw,
+                                            edge);
 }
 
 template <typename T, int NW, bool RAWOK = false>
 __device__ __forceinline__ void window_store(float* lds, const Fill<T>& f, const LdsWin& w, __amdgpu_buffer_rsrc_t rs,
-                                             int wp, const RawImg& im = RawImg{0, 0}, bool raw = false)
+                                             int wp, int r0, int cc, const RawImg& im = RawImg{0, 0},
+                                             bool raw = false)
 {
+    using FS = FillSplit<NW>;
+    constexpr int P = lds_pitch<NW>();
+    if (!f.on) return;
+    const int lo0 = r0 * P + 4 * cc;
 #pragma unroll
     for (int i = 0; i < kPre; ++i)
-        if (f.r0 + i * f.R < w.th) *reinterpret_cast<float4*>(&lds[f.lo0 + i * f.dlo]) = Chunk<T>::widen(f.v[i]);
+        if (r0 + i * FS::kRows < w.th)
+            *reinterpret_cast<float4*>(&lds[lo0 + i * FS::kRows * P]) = Chunk<T>::widen(f.v[i]);
     // rows past the prefetched ones, loaded and stored here
-    int r = f.r0 + kPre * f.R;
+    int r = r0 + kPre * FS::kRows;
     if (r >= w.th) return;
     const bool edge = RAWOK && raw && raw_edge(w, im);
-    const int cc = (f.lo0 - __mul24(f.r0, w.tw)) >> 2;
-    uint32_t px = f.px0 + (uint32_t)kPre * f.dpx;
-    int lo = f.lo0 + kPre * f.dlo;
-    for (; r < w.th; r += f.R, px += f.dpx, lo += f.dlo)
+    const uint32_t dpx = (uint32_t)__builtin_amdgcn_readfirstlane(__mul24(FS::kRows, wp));
+    uint32_t px = f.px0 + (uint32_t)kPre * dpx;
+    int lo = lo0 + kPre * FS::kRows * P;
+    for (; r < w.th; r += FS::kRows, px += dpx, lo += FS::kRows * P)
         *reinterpret_cast<float4*>(&lds[lo]) = Chunk<T>::widen(window_chunk<T, RAWOK>(rs, w, wp, r, cc, px, im, raw, edge));
 }
 
@@ -875,9 +931,14 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     // software pipeline: the window of the projection after this one is
     // loaded into registers while this one is sampled from LDS
     Fill<T> pre;
-    LdsWin wv(load_win(wins + po.k), kWave * NW);
+    constexpr int P = lds_pitch<NW>(), CAP = lds_cap<S, NW>();
+    // this thread's chunk slot in every window copy (a thread past the last
+    // full pass gets a slot past every window)
+    const int fr0 = (int)threadIdx.x / FillSplit<NW>::kCols;
+    const int fcc = fr0 < FillSplit<NW>::kRows ? (int)threadIdx.x % FillSplit<NW>::kCols : FillSplit<NW>::kCols;
+    LdsWin wv(load_win(wins + po.k), P, CAP);
     bool big = false;
-    if (wv.fits) window_prefetch<T, NW, RAWOK>(pre, wv, make_rsrc(po.img, a.proj_bytes), wp, im, raw);
+    if (wv.fits) window_prefetch<T, NW, RAWOK>(pre, wv, make_rsrc(po.img, a.proj_bytes), wp, fr0, fcc, im, raw);
     for (int n = 0; n < a.n_proj; ++n) {
         // this projection's set-up, loaded ahead of the window store so that
         // its latency passes behind the barriers: the tile's anchor record,
@@ -889,12 +950,12 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
         const unsigned char* img = po.img;
         po.advance(a);
         const bool more = n + 1 < a.n_proj;
-        const LdsWin wn(more ? load_win(wins + po.k) : Win{1, 0, 1, 0}, kWave * NW);
+        const LdsWin wn(more ? load_win(wins + po.k) : Win{1, 0, 1, 0}, P, CAP);
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(img, a.proj_bytes);
         const __amdgpu_buffer_rsrc_t rs_next = make_rsrc(po.img, a.proj_bytes);
         if (wv.fits) {
             __syncthreads();                                // previous projection's reads are done
-            window_store<T, NW, RAWOK>(lds, pre, wv, rs, wp, im, raw);
+            window_store<T, NW, RAWOK>(lds, pre, wv, rs, wp, fr0, fcc, im, raw);
             __syncthreads();
         }
         // every chunk of this window is in LDS by now; an unconditional wait
@@ -903,7 +964,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
         // per-thread branches it would otherwise wait for each load before
         // reusing its registers for the next)
         wait_vm_loads();
-        if (wn.fits) window_prefetch<T, NW, RAWOK>(pre, wn, rs_next, wp, im, raw);
+        if (wn.fits) window_prefetch<T, NW, RAWOK>(pre, wn, rs_next, wp, fr0, fcc, im, raw);
         if (wv.fits) {
             Strip st;
             float lox, hix, loy, hiy;
@@ -917,7 +978,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
                 hix = (float)(wv.c_hi - 1) - ax;
                 loy = (float)wv.j0 - ay;
                 hiy = (float)(wv.j1 - 1) - ay;
-                base = (__mul24((int)ay - wv.j0, wv.tw) + ((int)ax - wv.c_lo)) * 4;
+                base = (((int)ay - wv.j0) * P + ((int)ax - wv.c_lo)) * 4;
             } else {
                 // the tile's anchor, clamp range and LDS offset are shared by
                 // all lanes; each lane adds its column's offset
@@ -933,17 +994,29 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
                 hiy = an.hiy;
                 base = an.base;
             }
-            const uint32_t row_l = (uint32_t)wv.tw * 4;
+            // the four taps of a sample at LDS byte offset `off`: two reads of
+            // two floats each, the second row at the immediate offset P
+            auto taps = [&](uint32_t off, float& t00, float& t01, float& t10, float& t11) {
+                const float* q = reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off);
+                t00 = q[0];
+                t01 = q[1];
+                t10 = q[P];
+                t11 = q[P + 1];
+            };
+            // kGrp samples at a time: their positions first, then all their
+            // LDS reads, then the interpolations, so that a wave has the reads
+            // of several samples in flight instead of waiting for each
+            // sample's taps in turn
+            constexpr int kGrp = S < 4 ? S : 4;
+            constexpr int kMid = S / 2;
+            const bool neg = CWM == 2 ? cur.c[12] < 0.0 : an.neg != 0;
+            const float sgn = neg ? -1.0f : 1.0f;
             auto sample = [&](auto cw) {
-                const Walk<decltype(cw)::value> wk(st);
-                // kGrp samples at a time: their positions first, then all their
-                // LDS reads, then the interpolations, so that a wave has the
-                // reads of several samples in flight instead of waiting for
-                // each sample's taps in turn
-                constexpr int kGrp = S < 4 ? S : 4;
+                constexpr bool CW = decltype(cw)::value;
+                if (!CW && neg) negate_acc(acc);
+                const Walk<CW> wk(st, sgn);
 #pragma unroll
                 for (int g = 0; g < S; g += kGrp) {
-                    constexpr int kMid = S / 2;
                     uint32_t off[kGrp];
                     float sx[kGrp], sy[kGrp], wgt[kGrp];
 #pragma unroll
@@ -954,20 +1027,11 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
                         const float dy = __builtin_amdgcn_fmed3f(uy, loy, hiy);
                         sx[j] = __builtin_amdgcn_fractf(dx);
                         sy[j] = __builtin_amdgcn_fractf(dy);
-                        off[j] = tap_offset<2>(cvt_floor(dx), cvt_floor(dy), wv.tw, base);
+                        off[j] = tap_offset<2>(cvt_floor(dx), cvt_floor(dy), P, base);
                     }
                     float t00[kGrp], t01[kGrp], t10[kGrp], t11[kGrp];
 #pragma unroll
-                    for (int j = 0; j < kGrp; ++j) {
-                        const float* q0 =
-                            reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off[j]);
-                        const float* q1 =
-                            reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + off[j] + row_l);
-                        t00[j] = q0[0];
-                        t01[j] = q0[1];
-                        t10[j] = q1[0];
-                        t11[j] = q1[1];
-                    }
+                    for (int j = 0; j < kGrp; ++j) taps(off[j], t00[j], t01[j], t10[j], t11[j]);
 #pragma unroll
                     for (int j = 0; j < kGrp; ++j) {
                         const float top = fmaf(sx[j], t01[j] - t00[j], t00[j]);
@@ -976,15 +1040,46 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
                         acc[g + j] = fmaf(val, wgt[j], acc[g + j]);
                     }
                 }
+                if (!CW && neg) negate_acc(acc);
             };
-            const bool neg = CWM == 2 ? cur.c[12] < 0.0 : an.neg != 0;
-            if (neg) negate_acc(acc);
+            // u and w do not change along z (CWM 3): the lane's detector
+            // column, its fraction and 1/w hold for the whole strip, and only
+            // the row is stepped from voxel to voxel
+            auto sample_column = [&]() {
+                const float r = __builtin_amdgcn_rcpf(st.wb);
+                const float dx = __builtin_amdgcn_fmed3f(st.ub * r, lox, hix);
+                const float sx = __builtin_amdgcn_fractf(dx);
+                const int col = col_offset(cvt_floor(dx), base);
+                const float ay = st.vb * r, by = st.dv * r, r2 = r * r * sgn;
+#pragma unroll
+                for (int g = 0; g < S; g += kGrp) {
+                    uint32_t off[kGrp];
+                    float sy[kGrp];
+#pragma unroll
+                    for (int j = 0; j < kGrp; ++j) {
+                        const float dy = __builtin_amdgcn_fmed3f(fmaf((float)(g + j - kMid), by, ay), loy, hiy);
+                        sy[j] = __builtin_amdgcn_fractf(dy);
+                        off[j] = row_offset<4 * P>(cvt_floor(dy), col);
+                    }
+                    float t00[kGrp], t01[kGrp], t10[kGrp], t11[kGrp];
+#pragma unroll
+                    for (int j = 0; j < kGrp; ++j) taps(off[j], t00[j], t01[j], t10[j], t11[j]);
+#pragma unroll
+                    for (int j = 0; j < kGrp; ++j) {
+                        const float top = fmaf(sx, t01[j] - t00[j], t00[j]);
+                        const float bot = fmaf(sx, t11[j] - t10[j], t10[j]);
+                        const float val = fmaf(sy[j], bot - top, top);
+                        acc[g + j] = fmaf(val, r2, acc[g + j]);
+                    }
+                }
+            };
             if constexpr (CWM == 2) {
                 with_walk(cur.c, sample);
+            } else if constexpr (CWM == 3) {
+                sample_column();
             } else {
                 sample(std::integral_constant<bool, CWM == 1>{});
             }
-            if (neg) negate_acc(acc);
         }
         big |= !wv.fits && !wv.empty;
         wv = wn;
@@ -994,7 +1089,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
         // the staged images (kept out of the main loop, which then has a
         // single sampling path)
         for (int k = 0; k < a.n_proj; ++k) {
-            const LdsWin w(load_win(wins + k), kWave * NW);
+            const LdsWin w(load_win(wins + k), P, CAP);
             if (w.fits || w.empty) continue;
             const Coef cur = load_coef(a.coef, k);
             const bool neg = cur.c[12] < 0.0;
@@ -1055,9 +1150,10 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
 
 template <typename T, int S, int NW, int CWM, bool RAWOK = false>
 __global__ __launch_bounds__(kWave * NW)
-    __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<S, NW>(), lds_waves_per_eu<S, NW>()))) void bp_lds_kernel(TileArgs a)
+    __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<S, NW, CWM, RAWOK, sizeof(T) == 2>(),
+                                       lds_waves_per_eu<S, NW, CWM, RAWOK, sizeof(T) == 2>()))) void bp_lds_kernel(TileArgs a)
 {
-    __shared__ __attribute__((aligned(16))) float lds[kLdsCap];
+    __shared__ __attribute__((aligned(16))) float lds[lds_cap<S, NW>()];
     bp_lds_tile<T, S, NW, CWM, RAWOK>(a, xcd_remap(blockIdx.x, gridDim.x), a.rot_div, lds);
 }
 
@@ -1067,13 +1163,13 @@ __global__ __launch_bounds__(kWave * NW)
 // cheapest tiles.
 template <int S, int NW>
 __global__ __launch_bounds__(kWave * NW)
-    __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<S, NW>(), lds_waves_per_eu<S, NW>()))) void bp_batched_kernel(const TileArgs* __restrict__ scans,
+    __attribute__((amdgpu_waves_per_eu(batched_waves_per_eu<S>(), batched_waves_per_eu<S>()))) void bp_batched_kernel(const TileArgs* __restrict__ scans,
                                                                 const int32_t* __restrict__ item_begin,
                                                                 int n_scans, unsigned* counter,
                                                                 int total_items)
 {
     __shared__ int s_item;
-    __shared__ __attribute__((aligned(16))) float lds[kLdsCap];
+    __shared__ __attribute__((aligned(16))) float lds[lds_cap<S, NW>()];
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
         __syncthreads();
@@ -1423,18 +1519,22 @@ hipError_t bp_dispatch_t(const TileArgs& a, int nblocks, hipStream_t st)
 {
     dim3 grid(nblocks), block(kWave * NW);
     if (a.layout == 3) {
+        // the walk: 3 u and w constant along z, 1 w constant, 0 neither
+        auto by_walk = [&](auto k3, auto k1, auto k0) {
+            if (a.const_w == 2) launch_rotated(k3, a, grid, block, st);
+            else if (a.const_w == 1) launch_rotated(k1, a, grid, block, st);
+            else launch_rotated(k0, a, grid, block, st);
+        };
         if (a.dtype == 1)
-            a.const_w ? launch_rotated(bp_lds_kernel<__half, S, NW, 1>, a, grid, block, st)
-                      : launch_rotated(bp_lds_kernel<__half, S, NW, 0>, a, grid, block, st);
+            by_walk(bp_lds_kernel<__half, S, NW, 3>, bp_lds_kernel<__half, S, NW, 1>, bp_lds_kernel<__half, S, NW, 0>);
         else if (a.dtype == 2)
-            a.const_w ? launch_rotated(bp_lds_kernel<bf16_t, S, NW, 1>, a, grid, block, st)
-                      : launch_rotated(bp_lds_kernel<bf16_t, S, NW, 0>, a, grid, block, st);
+            by_walk(bp_lds_kernel<bf16_t, S, NW, 3>, bp_lds_kernel<bf16_t, S, NW, 1>,
+                    bp_lds_kernel<bf16_t, S, NW, 0>);
         else if (a.raw)
-            a.const_w ? launch_rotated(bp_lds_kernel<float, S, NW, 1, true>, a, grid, block, st)
-                      : launch_rotated(bp_lds_kernel<float, S, NW, 0, true>, a, grid, block, st);
+            by_walk(bp_lds_kernel<float, S, NW, 3, true>, bp_lds_kernel<float, S, NW, 1, true>,
+                    bp_lds_kernel<float, S, NW, 0, true>);
         else
-            a.const_w ? launch_rotated(bp_lds_kernel<float, S, NW, 1>, a, grid, block, st)
-                      : launch_rotated(bp_lds_kernel<float, S, NW, 0>, a, grid, block, st);
+            by_walk(bp_lds_kernel<float, S, NW, 3>, bp_lds_kernel<float, S, NW, 1>, bp_lds_kernel<float, S, NW, 0>);
         return hipGetLastError();
     }
     if (a.layout == 1)
@@ -1537,7 +1637,8 @@ hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, Anc*
     const int64_t n = (int64_t)a.tiles_x * a.tiles_y * a.tiles_z * a.n_proj;
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(window_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, strip, bx, by, out, anc);
+    const int pitch = waves == 1 ? lds_pitch<1>() : lds_pitch<4>();
+    hipLaunchKernelGGL(window_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, strip, bx, by, pitch, out, anc);
     return hipGetLastError();
 }
 
