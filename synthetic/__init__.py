@@ -144,22 +144,24 @@ def project_phantom(mats: np.ndarray, width: int, height: int, ph: Phantom,
     inv_a = torch.as_tensor(1.0 / ph.axes, device=dev)
     rotT = torch.as_tensor(ph.rot, device=dev).transpose(1, 2)  # world -> ellipsoid frame
     rho = torch.as_tensor(ph.rho, device=dev)
-    for k in range(N):
-        M = mats[k, :, :3]
-        Minv = np.linalg.inv(M)
-        C = torch.as_tensor(-Minv @ mats[k, :, 3], device=dev)
-        d = pix @ torch.as_tensor(Minv.T, device=dev)
-        d = d / torch.linalg.norm(d, dim=1, keepdim=True)
-        acc = torch.zeros(d.shape[0], dtype=torch.float64, device=dev)
+    # a batch of projections at a time (about 2^24 rays)
+    nb = max(1, (1 << 24) // (height * width))
+    for k0 in range(0, N, nb):
+        ks = range(k0, min(N, k0 + nb))
+        Minv = np.stack([np.linalg.inv(mats[k, :, :3]) for k in ks])                       # (b, 3, 3)
+        C = torch.as_tensor(np.stack([-Minv[i] @ mats[k, :, 3] for i, k in enumerate(ks)]), device=dev)  # (b, 3)
+        d = torch.einsum("pc,brc->bpr", pix, torch.as_tensor(Minv, device=dev))          # (b, HW, 3)
+        d = d / torch.linalg.norm(d, dim=2, keepdim=True)
+        acc = torch.zeros(d.shape[:2], dtype=torch.float64, device=dev)
         for e in range(len(ph.rho)):
-            o = (rotT[e] @ (C - cen[e])) * inv_a[e]
-            de = (d @ rotT[e].T) * inv_a[e]
-            A = (de * de).sum(1)
-            B = de @ o
-            Cc = (o * o).sum() - 1.0
+            o = ((C - cen[e]) @ rotT[e].T) * inv_a[e]                                       # (b, 3)
+            de = (d @ rotT[e].T) * inv_a[e]                                                 # (b, HW, 3)
+            A = (de * de).sum(2)
+            B = (de * o[:, None, :]).sum(2)
+            Cc = (o * o).sum(1, keepdim=True) - 1.0
             disc = B * B - A * Cc
             acc += torch.where(disc > 0, 2.0 * torch.sqrt(disc.clamp_min(0)) / A, 0.0) * rho[e]
-        out[k] = acc.reshape(height, width)
+        out[k0:k0 + len(ks)] = acc.reshape(len(ks), height, width)
     return out
 
 
@@ -299,3 +301,9 @@ def batched_scan_specs(n_scans: int = 16, seed: int = 100) -> list[ScanSpec]:
         sid = float(rng.uniform(600.0, 800.0))
         out.append(ScanSpec(L, 0.5, N, W, H, pix, sid, seed + i))
     return out
+
+
+def batched_phantom_scans(specs: list[ScanSpec], device="cpu") -> list[tuple[np.ndarray, torch.Tensor]]:
+    """Matrices and FP32 filtered projections of every scan's own seeded
+    phantom (seed = spec.seed), on that scan's C-arm."""
+    return [filtered_projections(sp.carm(), sp.seed, device=device) for sp in specs]

@@ -105,7 +105,9 @@ def test_batched_accumulate(fdk):
 
 def test_batched_every_item_once(fdk):
     """Many tiny scans (more work items than persistent workgroups, uneven
-    costs): every voxel of every scan is written exactly once."""
+    costs): every voxel of every scan is added exactly once.  The call
+    accumulates onto zeros, so a work item run twice would double its
+    voxels and one never run would leave them zero."""
     specs = [(8 + (i % 5) * 3, 6.0, 1 + (i % 4), 32, 24, 100 + i) for i in range(40)]
     scans = []
     for (L, voxel, N, W, H, seed) in specs:
@@ -113,8 +115,8 @@ def test_batched_every_item_once(fdk):
         mats = S.carm_matrices(carm)
         ones = torch.ones(N, H, W, device=DEV)
         scans.append(fdk.Scan(ones, fdk.Geometry(mats, W, H), fdk.Volume(L, voxel),
-                              torch.full((L, L, L), 1e30, device=DEV)))
-    fdk.backproject_batched(scans)
+                              torch.zeros((L, L, L), device=DEV)))
+    fdk.backproject_batched(scans, accumulate=True)
     torch.cuda.synchronize()
     for s, (L, voxel, N, W, H, seed) in zip(scans, specs):
         ref = oracle.backproject(L, voxel, s.geom.mats, np.ones((N, H, W), np.float32))
@@ -178,3 +180,67 @@ def test_batched_unstaged_edges_and_large_windows(fdk, strip, waves):
     for sc, (L, voxel, mats, q, qd, scale) in zip(scans, host):
         ref = oracle.backproject(L, voxel, mats, q.numpy())
         assert_parity(sc.out.cpu().numpy(), ref, what=f"unstaged L={L} W={sc.geom.width}")
+
+
+@pytest.mark.parametrize("layout", [3, 0])
+def test_batched_mixed_orbits(fdk, layout):
+    """A batch mixing circular scans (u and w constant along z) with tilted
+    ones (w varies along z): the persistent kernel decides the walk per
+    projection.  Against the oracle and against one launch per scan."""
+    specs = [(30, 4.0, 9, 128, 96, 0.0, 60), (28, 4.0, 7, 96, 72, 0.4, 61), (24, 5.0, 11, 128, 96, 0.4, 62),
+             (32, 3.5, 6, 160, 120, 0.0, 63)]
+    scans, refs = [], []
+    for L, voxel, n, W, H, tilt, seed in specs:
+        carm = S.CArm(n, W, H, pixel=384.0 / W, tilt_deg=tilt)
+        mats, q = S.filtered_projections(carm, seed)
+        scans.append(fdk.Scan(q.to(DEV), fdk.Geometry(mats, W, H), fdk.Volume(L, voxel),
+                              torch.full((L, L, L), float("nan"), device=DEV)))
+        refs.append(oracle.backproject(L, voxel, mats, q.numpy()))
+    fdk.set_tile(fdk.TUNE_BATCHED, 8, 4, layout)
+    fdk.set_tile(fdk.F32, 8, 4, layout)
+    try:
+        fdk.backproject_batched(scans)
+        singles = [fdk.backproject(s.proj, s.geom, s.vol) for s in scans]
+        torch.cuda.synchronize()
+    finally:
+        fdk.set_tile(fdk.TUNE_BATCHED, 0, 0)
+        fdk.set_tile(fdk.F32, 0, 0)
+    for sc, ref, one, sp in zip(scans, refs, singles, specs):
+        got = sc.out.cpu().numpy()
+        assert_parity(got, ref, what=f"mixed orbits layout {layout} tilt {sp[5]}")
+        assert oracle.rel_l2(got, one.cpu().numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("tile", [None, (32, 4, 3)])
+def test_batched_benchmark_scans(fdk, tile):
+    """The batched benchmark's 16 scans at their own sizes (L up to 256, N up
+    to 496, 1248x960 or 620x480 detectors, SID 600-800 mm, each with its own
+    seeded phantom), with the default tile and with the shape the autotuner
+    picks for them; every scan against the oracle at sampled voxels
+    (including its corners and centre).  The call accumulates onto zeros: a
+    work item run twice would show."""
+    specs = S.batched_scan_specs(16, seed=100)
+    data = S.batched_phantom_scans(specs, device=DEV)
+    scans = []
+    for sp, (mats, q) in zip(specs, data):
+        scans.append(fdk.Scan(q.contiguous(), fdk.Geometry(mats, sp.width, sp.height), fdk.Volume(sp.L, sp.voxel_mm),
+                              torch.zeros((sp.L, sp.L, sp.L), device=DEV)))
+    if tile is not None:
+        fdk.set_tile(fdk.TUNE_BATCHED, *tile)
+    try:
+        fdk.backproject_batched(scans, accumulate=True)
+        torch.cuda.synchronize()
+    finally:
+        fdk.set_tile(fdk.TUNE_BATCHED, 0, 0)
+    rng = np.random.default_rng(7)
+    for i, (sp, sc, (mats, q)) in enumerate(zip(specs, scans, data)):
+        L = sp.L
+        corners = np.array([[x, y, z] for x in (0, L - 1) for y in (0, L - 1) for z in (0, L - 1)])
+        xyz = np.concatenate([rng.integers(0, L, size=(300, 3)), corners, [[L // 2] * 3]])
+        ref = oracle.backproject_points(xyz, sp.voxel_mm, mats, q.cpu().numpy().astype(np.float64), L=L)
+        idx = torch.as_tensor(xyz.astype(np.int64), device=DEV)
+        got = sc.out[idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+        assert np.all(np.isfinite(got))
+        err = oracle.rel_l2(got, ref)
+        assert err <= 1e-5, f"scan {i} (L={L}, N={sp.n_proj}, {sp.width}x{sp.height}): rel L2 {err:.3e}"
+        assert np.abs(got - ref).max() <= 1e-4 * np.abs(ref).max(), f"scan {i}: element error"
