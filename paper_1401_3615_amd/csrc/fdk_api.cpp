@@ -412,7 +412,7 @@ struct DeviceState {
     hipStream_t capture_stream = nullptr;
     // preprocessing
     std::list<FilterEntry> filter_cache;   // most recent first
-    DevBuf filter_ws;
+    DevBuf filter_ws, filter_max;
     // iterative solvers: two projection-sized and two volume-sized vectors,
     // reduction partials and the solver's scalar state
     DevBuf it_p0, it_p1, it_v0, it_v1, it_part, it_st;
@@ -1233,16 +1233,9 @@ fdk_status fdk_filter_projections(const fdk_filter_geometry* g, const float* src
     if ((st = begin_call(*d, s)) != FDK_OK) return st;
     FilterEntry* f = nullptr;
     if ((st = filter_tables(*d, g, s, &f)) != FDK_OK) return st;
-    const size_t n_px = (size_t)g->n_proj * g->height * g->width;
-    float* out = static_cast<float*>(dst);
-    if (dtype != FDK_F32) {
-        hipError_t e = ensure(d->filter_ws, n_px * sizeof(float));
-        if (e != hipSuccess) return fail(FDK_E_NOMEM, "filter workspace: %s", hipGetErrorString(e));
-        out = static_cast<float*>(d->filter_ws.p);
-    }
     FilterArgs a;
     a.src = src;
-    a.dst = out;
+    a.dst = static_cast<float*>(dst);
     a.wc = static_cast<const double*>(f->wc.p);
     a.wp = static_cast<const double*>(f->wp.p);
     a.hs = static_cast<const double*>(f->hs.p);
@@ -1251,13 +1244,30 @@ fdk_status fdk_filter_projections(const fdk_filter_geometry* g, const float* src
     a.W = g->width;
     a.H = g->height;
     a.M = f->M;
+    a.maxbits = nullptr;
+    if (dtype == FDK_F32) {
+        ProfScope ps("filter", s);
+        HIP_TRY(launch_filter(a, s));
+        return end_call(*d, s);
+    }
+    // FP16/BF16 output: the stack is filtered into an FP32 workspace, the
+    // filter raising each projection's maximum as it writes, then packed in
+    // one pass (the maxima need no pass of their own)
+    const size_t n_px = (size_t)g->n_proj * g->height * g->width;
+    hipError_t e = ensure(d->filter_ws, n_px * sizeof(float));
+    if (e == hipSuccess) e = ensure(d->filter_max, (size_t)g->n_proj * sizeof(unsigned));
+    if (e != hipSuccess) return fail(FDK_E_NOMEM, "filter workspace: %s", hipGetErrorString(e));
+    unsigned* maxbits = static_cast<unsigned*>(d->filter_max.p);
+    HIP_TRY(launch_zero_u32(maxbits, g->n_proj, s));
+    a.dst = static_cast<float*>(d->filter_ws.p);
+    a.maxbits = maxbits;
     {
         ProfScope ps("filter", s);
         HIP_TRY(launch_filter(a, s));
     }
-    if (dtype != FDK_F32) {
+    {
         ProfScope ps("pack", s);
-        HIP_TRY(launch_pack(out, g->n_proj, g->width, g->height, dtype, dst, scale_out, s));
+        HIP_TRY(launch_pack_known_max(a.dst, g->n_proj, g->width, g->height, dtype, dst, maxbits, scale_out, s));
     }
     return end_call(*d, s);
 }
@@ -2058,6 +2068,7 @@ fdk_status fdk_release_workspace(void)
     }
     d.filter_cache.clear();
     release(d.filter_ws);
+    release(d.filter_max);
     for (DevBuf* b : {&d.it_p0, &d.it_p1, &d.it_v0, &d.it_v1, &d.it_part, &d.it_st}) release(*b);
     for (int b = 0; b < 2; ++b) {
         release(d.band[b]);

@@ -166,10 +166,26 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(FilterArgs f)
     // the conjugate of the result: row 0 real part, row 1 minus imaginary part
     float* d0 = f.dst + ((int64_t)k * f.H + j0) * f.W;
     float* d1 = d0 + f.W;
+    float m = 0.0f;
     for (int i = threadIdx.x; i < f.W; i += kFilterThreads) {
         const double2 v = x[i];
-        d0[i] = (float)v.x;
-        if (has1) d1[i] = (float)-v.y;
+        const float r0 = (float)v.x, r1 = has1 ? (float)-v.y : 0.0f;
+        d0[i] = r0;
+        if (has1) d1[i] = r1;
+        m = fmaxf(m, fmaxf(fabsf(r0), fabsf(r1)));
+    }
+    if (f.maxbits != nullptr) {
+        // the largest magnitude of the two rows, into the projection's maximum
+        // (the packing pass that follows needs it); the spectrum buffer is free now
+        float* red = reinterpret_cast<float*>(lds2);
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < kFilterThreads / 64; ++w) m = fmaxf(m, red[w]);
+            atomicMax(f.maxbits + k, __float_as_uint(m));
+        }
     }
 }
 

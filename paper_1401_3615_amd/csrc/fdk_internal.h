@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
 #include <stdint.h>
 
 namespace fdk {
@@ -102,6 +103,29 @@ int supported_band_group(int group);
 constexpr int kBandCap = 20480;   // FP64 accumulators of one workgroup's detector tiles (160 KiB of LDS)
 constexpr int kBandBorder = 2;    // border pixels around each tile that absorb off-tile taps
 
+// FP16/BF16 storage of projections: scale = max|p| / 2^14 (1 for an
+// all-zero projection), from the bits of max|p| (non-negative floats order
+// like their bits); stored value = round_to_nearest_even(p / scale).
+__device__ __forceinline__ float pack_scale(unsigned maxbits)
+{
+    const float m = __uint_as_float(maxbits);
+    return m > 0.0f ? m * 0x1p-14f : 1.0f;
+}
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);  // quiet NaN
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// dtype 1: FP16, 2: BF16
+__device__ __forceinline__ unsigned short pack_value(float p, float scale, int dtype)
+{
+    const float q = p / scale;
+    return dtype == 1 ? __half_as_ushort(__float2half_rn(q)) : f32_to_bf16_rne(q);
+}
+
 // FDK preprocessing: weights and ramp filtering of every row (fdk_filter.hip).
 struct FilterArgs {
     const float* src;            // n_proj x H x W line integrals
@@ -112,6 +136,8 @@ struct FilterArgs {
                                  // order the in-place FFT leaves the spectrum
     const double2* tw;           // M / 4 twiddles exp(-2 pi i t / M)
     int32_t n_proj, W, H, M;     // M: power of two >= 2 W - 1, 1.25 M FP64 complex fit 80 KiB of LDS
+    unsigned* maxbits;           // or null: bits of max |dst| per projection, raised by atomicMax
+                                 // (non-negative floats order like their bits)
 };
 hipError_t launch_filter(const FilterArgs& f, hipStream_t s);
 
@@ -170,6 +196,11 @@ hipError_t launch_unstage_add(const float* padded, float* out, int n, int W, int
                               uint64_t stride_elems, int accumulate, hipStream_t s);
 hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* dst, float* scale,
                        hipStream_t s);
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
+// FP16/BF16 packing of n projections whose max |src| bits are known (maxbits):
+// dst and scale as fdk_pack_projections
+hipError_t launch_pack_known_max(const float* src, int n, int W, int H, int dtype, void* dst, const unsigned* maxbits,
+                                 float* scale, hipStream_t s);
 // Windows (out) and sampling set-ups (anc, n_tiles x n_proj each; null: none,
 // for the persistent kernel, which anchors every lane itself) of an LDS launch
 // with the given tile shape.

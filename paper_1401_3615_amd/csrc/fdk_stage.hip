@@ -200,32 +200,33 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float* __restrict__ s
     }
 }
 
-__device__ __forceinline__ float pack_scale(unsigned maxbits)
-{
-    const float m = __uint_as_float(maxbits);
-    return m > 0.0f ? m * 0x1p-14f : 1.0f;
-}
-
-__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f)
-{
-    const uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);  // quiet NaN
-    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
-
+// scale_out: null (a later pass turns maxbits into the scales in place), or
+// where block 0 of each projection writes its scale
 __global__ __launch_bounds__(256) void convert_kernel(const float* __restrict__ src, int64_t per_proj,
                                                       const unsigned* __restrict__ maxbits, int dtype,
-                                                      unsigned short* __restrict__ dst)
+                                                      unsigned short* __restrict__ dst, float* scale_out)
 {
     const int k = blockIdx.y;
     const float s = pack_scale(maxbits[k]);
+    if (scale_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0) scale_out[k] = s;
     const float* p = src + (int64_t)k * per_proj;
     unsigned short* d = dst + (int64_t)k * per_proj;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per_proj;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const float q = p[i] / s;
-        d[i] = dtype == 1 ? __half_as_ushort(__float2half_rn(q)) : f32_to_bf16_rne(q);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if ((per_proj & 7) == 0 && ((uintptr_t)src & 15) == 0 && ((uintptr_t)dst & 15) == 0) {
+        // eight values per thread: two 16-byte loads, one 16-byte store
+        const float4* p4 = reinterpret_cast<const float4*>(p);
+        uint4* d8 = reinterpret_cast<uint4*>(d);
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (per_proj >> 3); i += stride) {
+            const float4 a = p4[2 * i], b = p4[2 * i + 1];
+            auto two = [&](float x, float y) {
+                return (uint32_t)pack_value(x, s, dtype) | ((uint32_t)pack_value(y, s, dtype) << 16);
+            };
+            d8[i] = make_uint4(two(a.x, a.y), two(a.z, a.w), two(b.x, b.y), two(b.z, b.w));
+        }
+        return;
     }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per_proj; i += stride)
+        d[i] = pack_value(p[i], s, dtype);
 }
 
 __global__ void finalize_scale_kernel(unsigned* __restrict__ maxbits, int n)
@@ -337,6 +338,25 @@ hipError_t launch_unstage_add(const float* padded, float* out, int n, int W, int
     return hipGetLastError();
 }
 
+hipError_t launch_pack_known_max(const float* src, int n, int W, int H, int dtype, void* dst, const unsigned* maxbits,
+                                 float* scale, hipStream_t s)
+{
+    const int64_t per = (int64_t)W * H;
+    int bx = (int)((per + 256 * 16 - 1) / (256 * 16));
+    if (bx < 1) bx = 1;
+    if (bx > 1024) bx = 1024;
+    hipLaunchKernelGGL(convert_kernel, dim3(bx, n), dim3(256), 0, s, src, per, maxbits, dtype, (unsigned short*)dst,
+                       scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* dst, float* scale,
                        hipStream_t s)
 {
@@ -348,7 +368,7 @@ hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* d
     if (bx > 1024) bx = 1024;
     hipLaunchKernelGGL(absmax_kernel, dim3(bx, n), dim3(256), 0, s, src, per, bits);
     hipLaunchKernelGGL(convert_kernel, dim3(bx, n), dim3(256), 0, s, src, per, bits, dtype,
-                       (unsigned short*)dst);
+                       (unsigned short*)dst, nullptr);
     hipLaunchKernelGGL(finalize_scale_kernel, dim3((n + 255) / 256), dim3(256), 0, s, bits, n);
     return hipGetLastError();
 }
