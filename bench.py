@@ -115,9 +115,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    ap.add_argument("--legs", default="fp16,bf16,tilted,adjoint,iterative,batched,slab1024,streamed,filter",
+    ap.add_argument("--legs", default="fp16,bf16,tilted,adjoint,iterative,batched,slab1024,streamed,filter,xxl",
                     help="comma list of extra legs (fp16,bf16,tilted,adjoint,iterative,batched,slab1024,"
-                         "streamed,filter) or 'none'")
+                         "streamed,filter,xxl) or 'none'")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only warm-up and timed FP32 steps (for profiler runs)")
     args = ap.parse_args()
@@ -349,6 +349,34 @@ def main() -> int:
             f"{extra['streamed1024_gups']:.1f} GUp/s; volume in host memory too: {mh:.1f} ms, "
             f"{extra['streamed1024_host_volume_gups']:.1f} GUp/s")
         del hv, host_q
+
+    # ---------------------------------------------------------------- large detector
+    if "xxl" in legs:
+        # the paper's outlook to industrial scanners: 8 projections of 10000 x 10000
+        # pixels (381 MiB each) in pinned host memory, streamed one detector row
+        # band per 32-plane slab into the middle 256 planes of a 4096^2 grid at
+        # 0.25 mm (16 GiB on the device)
+        xc = S.xxl_carm(8)
+        t0 = time.time()
+        xm, xq = S.filtered_projections(xc, seed=0, device=dev)
+        xhost = xq.cpu().pin_memory()
+        del xq
+        torch.cuda.empty_cache()
+        log(f"xxl: 8 filtered 10000x10000 projections generated in {time.time() - t0:.1f} s")
+        xg = fdk.Geometry(xm, xc.width, xc.height)
+        xv = fdk.Volume(4096, 0.25).slab(1920, 256)
+        xrows, _ = fdk.streamed_plan(xg, xv, 32)
+        xh2d = float(xrows.sum()) * 8 * xc.width * 4
+        xout = torch.empty((256, 4096, 4096), dtype=torch.float32, device=dev)
+        mx = time_steps(lambda: fdk.backproject_streamed(xhost, xg, xv, 32, out=xout), 2, 1, stream)
+        xup = 4096 * 4096 * 256 * 8
+        extra["xxl_gups"] = xup / (mx * 1e-3) / 1e9
+        extra["xxl_ms_per_step"] = mx
+        extra["xxl_h2d_gb"] = xh2d / 1e9
+        extra["xxl_config"] = "8 x 10000x10000 fp32 projections (pinned host) -> 4096^2 x 256 planes @0.25mm, 32-plane slabs"
+        log(f"xxl: 4096^2 x 256 from 8 x 10000x10000 projections in host memory ({xh2d / 1e9:.2f} GB of row bands): "
+            f"{mx:.1f} ms, {extra['xxl_gups']:.1f} GUp/s")
+        del xout, xhost
 
     # ---------------------------------------------------------------- batched
     if "batched" in legs:

@@ -307,3 +307,12 @@ def batched_phantom_scans(specs: list[ScanSpec], device="cpu") -> list[tuple[np.
     """Matrices and FP32 filtered projections of every scan's own seeded
     phantom (seed = spec.seed), on that scan's C-arm."""
     return [filtered_projections(sp.carm(), sp.seed, device=device) for sp in specs]
+
+
+def xxl_carm(n_proj: int) -> CArm:
+    """A large industrial cone-beam scanner with a 10000 x 10000 detector
+    (381 MiB per FP32 projection): SID 2000 mm, SDD 3000 mm, 0.15 mm pixels
+    (1.5 m detector, 1 m field at the isocentre), short scan of 210 degrees
+    (fan half-angle 14.0 degrees).  A 0.25 mm voxel then spans 2.5 pixels at
+    the isocentre, as a 0.5 mm voxel does on the 1248 x 960 C-arm."""
+    return CArm(n_proj, 10000, 10000, sid=2000.0, sdd=3000.0, pixel=0.15, arc_deg=210.0)
