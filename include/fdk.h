@@ -353,9 +353,10 @@ fdk_status fdk_sirt(const fdk_volume* vol, const fdk_projections* proj, float* v
  * slot) or FDK_TUNE_ADJOINT (the forward projector).  For the forward
  * projector, layout 4 (the default) gives each workgroup a detector tile of
  * `strip` rows (1 <= strip, (strip + 4) * 5 * waves <= 20480) by
- * min(width, 20480 / ((strip + 4) * waves) - 4) pixels in `waves` projections
- * (1, 2, 4 or 8), accumulated in FP64 in LDS inside a two-pixel border and
- * written once; layout 0 scatters
+ * min(width, 20480 / ((strip + 4) * waves) - 4) pixels (one fewer where the
+ * row pitch, rounded up to an odd number of accumulators, would not fit) in
+ * `waves` projections (1, 2, 4 or 8), accumulated in FP64 in LDS inside a
+ * two-pixel border and written once; layout 0 scatters
  * every voxel straight to global memory with float atomics (tile shapes as for
  * the backprojection).
  * fdk_set_tile pins the choice for a dtype (strip = waves = 0 restores the

@@ -941,6 +941,8 @@ static fdk_status forwardproject_tiles(const fdk_volume* vol, const float* volum
     BandArgs b{};
     b.th = std::min(t.strip, geom->height);
     b.tw = std::min(geom->width, kBandCap / ((b.th + 2 * kBandBorder) * t.waves) - 2 * kBandBorder);
+    // the kernel rounds the tile pitch up to an odd number of accumulators
+    if ((int64_t)((b.tw + 2 * kBandBorder) | 1) * (b.th + 2 * kBandBorder) * t.waves > kBandCap) b.tw -= 1;
     b.tiles_u = (geom->width + b.tw - 1) / b.tw;
     b.tiles_v = (geom->height + b.th - 1) / b.th;
     if ((int64_t)b.tiles_u * b.tiles_v * ((geom->n_proj + t.waves - 1) / t.waves) > 0x7fffffffLL)

@@ -93,7 +93,7 @@ struct BandArgs {
     int32_t tw, th, tiles_u, tiles_v;
     float out_scale;
     int32_t accumulate;
-    int32_t const_w;             // 1: w does not depend on z for any projection
+    int32_t const_w;             // 1: w does not depend on z for any projection, 2: neither u nor w
 };
 
 // group = projections per workgroup (1, 2, 4 or 8); P (tw + 2 kBandBorder)

@@ -84,6 +84,14 @@ __device__ __forceinline__ uint32_t row_offset(int j0, int col)
     return (uint32_t)off;
 }
 
+// j0 * rowb + col, one VALU op (|j0|, rowb < 2^23, rowb in a register).
+__device__ __forceinline__ uint32_t row_offset_dyn(int j0, int rowb, int col)
+{
+    int off;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(off) : "v"(j0), "s"(rowb), "v"(col));
+    return (uint32_t)off;
+}
+
 // One detector row of the 2x2 tap block: the taps (i0, i0+1) come from one
 // load at byte offset `off` (+ `soff`), and row() returns their linear
 // interpolation  l + sx (r - l)  in FP32.
@@ -1314,8 +1322,10 @@ __device__ __forceinline__ BandCol band_interval(float u0, float v0, float w0, f
 }
 
 // CW: w does not change along z for any projection (one 1/w per column and
-// projection; the remainders step linearly).
-template <int P, bool CW>
+// projection; the remainders step linearly).  CU (with CW): u does not change
+// either (a circular orbit about z), so a column's detector column, its
+// fraction and clamped tile column hold for all its planes.
+template <int P, bool CW, bool CU = false>
 __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
 {
     // P tiles of FP64 accumulators, each th x tw pixels inside a border of
@@ -1330,7 +1340,9 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
     const int i0 = tu * b.tw, i1 = min(i0 + b.tw, b.W);
     const int j0 = tv * b.th, j1 = min(j0 + b.th, b.H);
     const int tw = i1 - i0, th = j1 - j0;
-    const int tp = tw + 2 * kBandBorder, tsz = tp * (th + 2 * kBandBorder);   // pitch, size of one tile
+    // pitch (odd, so the FP64 accumulators of one column in neighbouring rows
+    // fall on different LDS banks) and size of one tile
+    const int tp = (tw + 2 * kBandBorder) | 1, tsz = tp * (th + 2 * kBandBorder);
     for (int e = threadIdx.x; e < P * tsz; e += kBandThreads) lds[e] = 0.0;
     __syncthreads();
     const double* coef = b.coef + 16 * k0;
@@ -1350,119 +1362,187 @@ __global__ __launch_bounds__(kBandThreads) void fp_band_kernel(BandArgs b)
     const bool along_x = fabs(coef[0] * coef[11] - coef[3] * coef[8]) >= fabs(coef[1] * coef[11] - coef[3] * coef[9]);
     const int px = along_x ? pa : pb, py = along_x ? pb : pa;
     const int nbx = (b.L + 31) >> 5, nblk = nbx * nbx;
-    for (int blk = 0; blk < nblk; ++blk) {
-        const int by = blk / nbx;
-        const int x = (blk - by * nbx) * 32 + px, y = by * 32 + py;
-        if (x >= b.L || y >= b.L) continue;
-        const float xf = (float)(x - b.ctr), yf = (float)(y - b.ctr);
-        BandCol iv[P];
-        float za = zhi + 1.0f, zb = zlo - 1.0f;
+    // Block pruning: a 32 x 32 block of columns whose eight corner voxels (all
+    // planes of the launch) project, for every projection of the group, to a
+    // box that misses the tile cannot put a tap into it (w > 0 on the box, so
+    // the projected box lies in the hull of its corners).  The waves test 64
+    // blocks at a time, one per lane, and walk only the blocks that can hit.
+    auto block_hits = [&](int blk) {
+        const int by = blk / nbx, bx = blk - by * nbx;
+        const float xa = (float)(bx * 32 - b.ctr), xb = (float)(min(bx * 32 + 31, b.L - 1) - b.ctr);
+        const float ya = (float)(by * 32 - b.ctr), yb = (float)(min(by * 32 + 31, b.L - 1) - b.ctr);
+        constexpr float m = 1.5f;   // pixels, far above the FP32 rounding of the corner projections
+        bool hit = false;
+        for (int p = 0; p < np; ++p) {
+            const double* c = coef + 16 * p;
+            float c32[12];
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            iv[p].za = 1.0f;
-            iv[p].zb = 0.0f;
-            if (p < np) {
-                const double* c = coef + 16 * p;
-                const float u0 = fmaf(xf, (float)c[0], fmaf(yf, (float)c[1], (float)c[3]));
-                const float v0 = fmaf(xf, (float)c[4], fmaf(yf, (float)c[5], (float)c[7]));
-                const float w0 = fmaf(xf, (float)c[8], fmaf(yf, (float)c[9], (float)c[11]));
-                iv[p] = band_interval(u0, v0, w0, (float)c[2], (float)c[6], (float)c[10], zlo, zhi, tlo, thi, slo,
-                                      shi);
-                if (iv[p].za <= iv[p].zb) {
-                    za = fminf(za, iv[p].za);
-                    zb = fmaxf(zb, iv[p].zb);
+            for (int i = 0; i < 12; ++i) c32[i] = (float)c[i];
+            float ulo = 3.0e38f, uhi = -3.0e38f, vlo = 3.0e38f, vhi = -3.0e38f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float X = (q & 1) ? xb : xa, Y = (q & 2) ? yb : ya, Z = (q & 4) ? zhi : zlo;
+                const float u = fmaf(X, c32[0], fmaf(Y, c32[1], fmaf(Z, c32[2], c32[3])));
+                const float v = fmaf(X, c32[4], fmaf(Y, c32[5], fmaf(Z, c32[6], c32[7])));
+                const float r = __builtin_amdgcn_rcpf(fmaf(X, c32[8], fmaf(Y, c32[9], fmaf(Z, c32[10], c32[11]))));
+                ulo = fminf(ulo, u * r);
+                uhi = fmaxf(uhi, u * r);
+                vlo = fminf(vlo, v * r);
+                vhi = fmaxf(vhi, v * r);
+            }
+            hit = hit || (uhi > slo - 1.0f - m && ulo < shi + m && vhi > tlo - 1.0f - m && vlo < thi + m);
+        }
+        return hit;
+    };
+    for (int c0 = 0; c0 < nblk; c0 += kWave) {
+        uint64_t todo = __builtin_amdgcn_ballot_w64(c0 + lane < nblk && block_hits(c0 + lane));
+        while (todo != 0) {
+            const int blk = c0 + (int)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int by = blk / nbx;
+            const int x = (blk - by * nbx) * 32 + px, y = by * 32 + py;
+            if (x >= b.L || y >= b.L) continue;
+            const float xf = (float)(x - b.ctr), yf = (float)(y - b.ctr);
+            BandCol iv[P];
+            float za = zhi + 1.0f, zb = zlo - 1.0f;
+    #pragma unroll
+            for (int p = 0; p < P; ++p) {
+                iv[p].za = 1.0f;
+                iv[p].zb = 0.0f;
+                if (p < np) {
+                    const double* c = coef + 16 * p;
+                    const float u0 = fmaf(xf, (float)c[0], fmaf(yf, (float)c[1], (float)c[3]));
+                    const float v0 = fmaf(xf, (float)c[4], fmaf(yf, (float)c[5], (float)c[7]));
+                    const float w0 = fmaf(xf, (float)c[8], fmaf(yf, (float)c[9], (float)c[11]));
+                    iv[p] = band_interval(u0, v0, w0, (float)c[2], (float)c[6], (float)c[10], zlo, zhi, tlo, thi, slo,
+                                          shi);
+                    if (iv[p].za <= iv[p].zb) {
+                        za = fminf(za, iv[p].za);
+                        zb = fmaxf(zb, iv[p].zb);
+                    }
                 }
             }
-        }
-        if (za > zb) continue;
-        const int zl_a = (int)za + b.ctr - b.z_begin, zl_b = (int)zb + b.ctr - b.z_begin;
-        const int zmid = (zl_a + zl_b) >> 1;
-        const double xd = (double)(x - b.ctr), yd = (double)(y - b.ctr);
-        const double zd = (double)(b.z_begin + zmid - b.ctr);
-        // per projection: FP64 anchor at the middle plane, FP32 remainders
-        float sub[P], svb[P], swb[P], sdu[P], sdv[P];
-        int oi[P], oj[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const double* c = coef + 16 * p;
-            const bool on = p < np && iv[p].za <= iv[p].zb;
-            const double ub = fma(xd, c[0], fma(yd, c[1], fma(zd, c[2], c[3])));
-            const double vb = fma(xd, c[4], fma(yd, c[5], fma(zd, c[6], c[7])));
-            const double wb = fma(xd, c[8], fma(yd, c[9], fma(zd, c[10], c[11])));
-            const float wf = (float)wb;
-            const float rf = __builtin_amdgcn_rcpf(wf);
-            const float fau = fminf(fmaxf(rintf((float)ub * rf), -1.0e6f), 1.0e6f);
-            const float fav = fminf(fmaxf(rintf((float)vb * rf), -1.0e6f), 1.0e6f);
-            sub[p] = (float)fma(-(double)fau, wb, ub);
-            svb[p] = (float)fma(-(double)fav, wb, vb);
-            swb[p] = wf;
-            sdu[p] = (float)fma(-(double)fau, c[10], c[2]);
-            sdv[p] = (float)fma(-(double)fav, c[10], c[6]);
-            if (CW) {   // u/w and v/w themselves step linearly; swb holds out_scale / w^2
-                sub[p] *= rf;
-                svb[p] *= rf;
-                sdu[p] *= rf;
-                sdv[p] *= rf;
-                swb[p] = rf * rf * b.out_scale;
-            }
-            // tap (i, j) relative to the tile; an inactive projection gets a
-            // row offset that keeps every tap outside
-            oi[p] = (int)fau + b.cu - i0;
-            oj[p] = on ? (int)fav + b.cv - j0 : -(1 << 28);
-        }
-        // voxel values four planes per step, the next four in flight while the
-        // current ones are scattered (the loads are unconditional, past the
-        // interval from its last plane, so the waits for them can be partial)
-        const float* in = b.vol + (int64_t)y * b.L + x;
-        // t: plane offset from the anchor plane
-        auto scatter = [&](float t, float val0) {
-            const float vs = CW ? val0 : val0 * b.out_scale;   // CW: the scale is in swb
-#pragma unroll
+            if (za > zb) continue;
+            const int zl_a = (int)za + b.ctr - b.z_begin, zl_b = (int)zb + b.ctr - b.z_begin;
+            const int zmid = (zl_a + zl_b) >> 1;
+            const double xd = (double)(x - b.ctr), yd = (double)(y - b.ctr);
+            const double zd = (double)(b.z_begin + zmid - b.ctr);
+            // per projection: FP64 anchor at the middle plane, FP32 remainders
+            float sub[P], svb[P], swb[P], sdu[P], sdv[P];
+            int oi[P], oj[P];
+            float rlo[P], rhi[P];
+            int rcol[P];
+            double csx[P], comsx[P];   // CU: the column's fraction sx and 1 - sx
+            int ccol[P];               // CU: byte offset of its clamped tile column (row 0 of the border)
+    #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const double* c = coef + 16 * p;
-                float ux, uy, wgt;
-                if (CW) {
-                    ux = fmaf(t, sdu[p], sub[p]);
-                    uy = fmaf(t, sdv[p], svb[p]);
-                    wgt = swb[p];
-                } else {
-                    const float r = __builtin_amdgcn_rcpf(fmaf(t, (float)c[10], swb[p]));
-                    ux = fmaf(t, sdu[p], sub[p]) * r;
-                    uy = fmaf(t, sdv[p], svb[p]) * r;
-                    wgt = r * r;
+                const bool on = p < np && iv[p].za <= iv[p].zb;
+                const double ub = fma(xd, c[0], fma(yd, c[1], fma(zd, c[2], c[3])));
+                const double vb = fma(xd, c[4], fma(yd, c[5], fma(zd, c[6], c[7])));
+                const double wb = fma(xd, c[8], fma(yd, c[9], fma(zd, c[10], c[11])));
+                const float wf = (float)wb;
+                const float rf = __builtin_amdgcn_rcpf(wf);
+                const float fau = fminf(fmaxf(rintf((float)ub * rf), -1.0e6f), 1.0e6f);
+                const float fav = fminf(fmaxf(rintf((float)vb * rf), -1.0e6f), 1.0e6f);
+                sub[p] = (float)fma(-(double)fau, wb, ub);
+                svb[p] = (float)fma(-(double)fav, wb, vb);
+                swb[p] = wf;
+                sdu[p] = (float)fma(-(double)fau, c[10], c[2]);
+                sdv[p] = (float)fma(-(double)fav, c[10], c[6]);
+                if (CW) {   // u/w and v/w themselves step linearly; swb holds out_scale / w^2
+                    sub[p] *= rf;
+                    svb[p] *= rf;
+                    sdu[p] *= rf;
+                    sdv[p] *= rf;
+                    swb[p] = rf * rf * b.out_scale;
                 }
-                const float dx = __builtin_amdgcn_fmed3f(ux, -2.0e6f, 2.0e6f);
-                const float dy = __builtin_amdgcn_fmed3f(uy, -2.0e6f, 2.0e6f);
-                const float sx = __builtin_amdgcn_fractf(dx), sy = __builtin_amdgcn_fractf(dy);
-                const int ti = oi[p] + cvt_floor(dx), tj = oj[p] + cvt_floor(dy);
-                const float val = vs * wgt;
-                const float bw = val * sy, tv = val - bw;
-                // a tap pair off the tile is clamped into the border, where
-                // both taps stay (the border is never written back)
-                const int ci = min(max(ti, -kBandBorder), tw);
-                const int cj = min(max(tj, -kBandBorder), th);
-                double* tl = lds + (p * tsz + kBandBorder * tp + kBandBorder) + __mul24(cj, tp) + ci;
-                __hip_atomic_fetch_add(tl, (double)(tv - tv * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                __hip_atomic_fetch_add(tl + 1, (double)(tv * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                __hip_atomic_fetch_add(tl + tp, (double)(bw - bw * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                __hip_atomic_fetch_add(tl + tp + 1, (double)(bw * sx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                // tap (i, j) relative to the tile; an inactive projection gets a
+                // row offset that keeps every tap outside
+                oi[p] = (int)fau + b.cu - i0;
+                oj[p] = on ? (int)fav + b.cv - j0 : -(1 << 28);
+                if (CU) {
+                    const float dx = __builtin_amdgcn_fmed3f(sub[p], -2.0e6f, 2.0e6f);
+                    const float fx = __builtin_amdgcn_fractf(dx);
+                    csx[p] = (double)fx;
+                    comsx[p] = 1.0 - (double)fx;
+                    ccol[p] = (p * tsz + min(max(oi[p] + cvt_floor(dx), -kBandBorder), tw) + kBandBorder) * 8;
+                }
+                // the row of a sample is clamped into [-rb, th + kBandBorder - rb]
+                // (rb = its anchor row from the first border row), and rb is
+                // added in the byte offset: a tap pair off the tile lands in the
+                // border, where both taps stay (the border is never written
+                // back); an inactive projection sends every tap to border row 0
+                const int rb = on ? oj[p] + kBandBorder : 0;
+                rlo[p] = on ? (float)-rb : 0.0f;
+                rhi[p] = on ? (float)(th + kBandBorder - rb) + 0.5f : 0.5f;
+                rcol[p] = rb * tp * 8;
             }
-        };
-        const float* pz = in + (int64_t)zl_a * plane;   // first plane of the current step
-        const float* plast = in + (int64_t)zl_b * plane;
-        float cur[4], nxt[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cur[j] = *(zl_a + j <= zl_b ? pz + j * plane : plast);
-        for (int z4 = zl_a; z4 <= zl_b; z4 += 4) {
-            pz += 4 * plane;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) nxt[j] = *(z4 + 4 + j <= zl_b ? pz + j * plane : plast);
-            const float tz = (float)(z4 - zmid);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (z4 + j <= zl_b && cur[j] != 0.0f) scatter(tz + (float)j, cur[j]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
+            // voxel values four planes per step, the next four in flight while the
+            // current ones are scattered (the loads are unconditional, past the
+            // interval from its last plane, so the waits for them can be partial)
+            const float* in = b.vol + (int64_t)y * b.L + x;
+            // t: plane offset from the anchor plane
+            auto scatter = [&](float t, float val0) {
+                const float vs = CW ? val0 : val0 * b.out_scale;   // CW: the scale is in swb
+    #pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const double* c = coef + 16 * p;
+                    float ux, uy, wgt;
+                    if (CW) {
+                        ux = fmaf(t, sdu[p], sub[p]);
+                        uy = fmaf(t, sdv[p], svb[p]);
+                        wgt = swb[p];
+                    } else {
+                        const float r = __builtin_amdgcn_rcpf(fmaf(t, (float)c[10], swb[p]));
+                        ux = fmaf(t, sdu[p], sub[p]) * r;
+                        uy = fmaf(t, sdv[p], svb[p]) * r;
+                        wgt = r * r;
+                    }
+                    const float dy = __builtin_amdgcn_fmed3f(uy, rlo[p], rhi[p]);
+                    const float sy = __builtin_amdgcn_fractf(dy);
+                    double sx, omsx;
+                    int col;
+                    if (CU) {
+                        sx = csx[p];
+                        omsx = comsx[p];
+                        col = ccol[p];
+                    } else {
+                        const float dx = __builtin_amdgcn_fmed3f(ux, -2.0e6f, 2.0e6f);
+                        const float fx = __builtin_amdgcn_fractf(dx);
+                        sx = (double)fx;
+                        omsx = 1.0 - sx;
+                        col = (p * tsz + min(max(oi[p] + cvt_floor(dx), -kBandBorder), tw) + kBandBorder) * 8;
+                    }
+                    // the four bilinear weights times the value, in FP64
+                    const double val = (double)(vs * wgt);
+                    const double bw = val * (double)sy, tv = val - bw;
+                    char* base = reinterpret_cast<char*>(lds);
+                    const uint32_t off = row_offset_dyn(cvt_floor(dy), tp * 8, col + rcol[p]);
+                    double* tl = reinterpret_cast<double*>(base + off);
+                    double* bl = reinterpret_cast<double*>(base + off + tp * 8);
+                    __hip_atomic_fetch_add(tl, tv * omsx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add(tl + 1, tv * sx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add(bl, bw * omsx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add(bl + 1, bw * sx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            };
+            const float* pz = in + (int64_t)zl_a * plane;   // first plane of the current step
+            const float* plast = in + (int64_t)zl_b * plane;
+            float cur[4], nxt[4];
+    #pragma unroll
+            for (int j = 0; j < 4; ++j) cur[j] = *(zl_a + j <= zl_b ? pz + j * plane : plast);
+            for (int z4 = zl_a; z4 <= zl_b; z4 += 4) {
+                pz += 4 * plane;
+    #pragma unroll
+                for (int j = 0; j < 4; ++j) nxt[j] = *(z4 + 4 + j <= zl_b ? pz + j * plane : plast);
+                const float tz = (float)(z4 - zmid);
+    #pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (z4 + j <= zl_b && cur[j] != 0.0f) scatter(tz + (float)j, cur[j]);
+    #pragma unroll
+                for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
+            }
         }
     }
     __syncthreads();
@@ -1644,33 +1724,33 @@ hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, Anc*
 
 int supported_band_group(int p) { return p == 1 || p == 2 || p == 4 || p == 8; }
 
-template <int P, bool CW>
+template <int P, bool CW, bool CU = false>
 static hipError_t launch_band(const BandArgs& b, hipStream_t s)
 {
     const int groups = (b.n_proj + P - 1) / P;
     const int64_t blocks = (int64_t)b.tiles_u * b.tiles_v * groups;
-    const size_t lds = (size_t)P * (b.tw + 2 * kBandBorder) * (b.th + 2 * kBandBorder) * sizeof(double);
+    const size_t lds = (size_t)P * ((b.tw + 2 * kBandBorder) | 1) * (b.th + 2 * kBandBorder) * sizeof(double);
     if (blocks > 0x7fffffffLL || lds > (size_t)kBandCap * sizeof(double)) return hipErrorInvalidValue;
     static bool attr_set = false;
     if (!attr_set) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fp_band_kernel<P, CW>),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fp_band_kernel<P, CW, CU>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  kBandCap * (int)sizeof(double));
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((fp_band_kernel<P, CW>), dim3((unsigned)blocks), dim3(kBandThreads), lds, s, b);
+    hipLaunchKernelGGL((fp_band_kernel<P, CW, CU>), dim3((unsigned)blocks), dim3(kBandThreads), lds, s, b);
     return hipGetLastError();
 }
 
 hipError_t launch_fp_band(const BandArgs& b, int group, hipStream_t s)
 {
-    const bool cw = b.const_w != 0;
+    const int cw = b.const_w;   // 2: u and w constant along z, 1: w, 0: neither
     switch (group) {
-    case 1: return cw ? launch_band<1, true>(b, s) : launch_band<1, false>(b, s);
-    case 2: return cw ? launch_band<2, true>(b, s) : launch_band<2, false>(b, s);
-    case 4: return cw ? launch_band<4, true>(b, s) : launch_band<4, false>(b, s);
-    case 8: return cw ? launch_band<8, true>(b, s) : launch_band<8, false>(b, s);
+    case 1: return cw == 2 ? launch_band<1, true, true>(b, s) : cw ? launch_band<1, true>(b, s) : launch_band<1, false>(b, s);
+    case 2: return cw == 2 ? launch_band<2, true, true>(b, s) : cw ? launch_band<2, true>(b, s) : launch_band<2, false>(b, s);
+    case 4: return cw == 2 ? launch_band<4, true, true>(b, s) : cw ? launch_band<4, true>(b, s) : launch_band<4, false>(b, s);
+    case 8: return cw == 2 ? launch_band<8, true, true>(b, s) : cw ? launch_band<8, true>(b, s) : launch_band<8, false>(b, s);
     default: return hipErrorInvalidValue;
     }
 }
