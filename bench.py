@@ -45,15 +45,17 @@ def log(msg: str) -> None:
 
 def bp_kernel_name(fdk, vol, geom) -> str:
     """Name of the FP32 backprojection kernel the library launches for `vol`
-    (the LDS kernel is instantiated for w constant along z, i.e. a zero
-    z-coefficient in every matrix's third row, or not, and for reading
-    staged images or the caller's stack in place, which it does for grids
-    with fewer than one voxel per eight projection pixels)."""
+    (the LDS kernel is instantiated for u and w constant along z (3: zero
+    z-coefficients in every matrix's first and third rows), w constant (1) or
+    neither (0), and for reading staged images or the caller's stack in
+    place, which it does for grids with fewer than one voxel per eight
+    projection pixels)."""
     import numpy as np
     strip, waves, layout = fdk.get_tile(vol, fdk.F32)
     if layout == 3:
         m = np.asarray(geom.mats).reshape(-1, 3, 4)
-        cw = int(bool(np.all(m[:, 2, 2] == 0.0)))
+        w_const = bool(np.all(m[:, 2, 2] == 0.0))
+        cw = 3 if w_const and bool(np.all(m[:, 0, 2] == 0.0)) else int(w_const)
         pixels = len(m) * geom.width * geom.height
         in_place = vol.planes * vol.L * vol.L * 8 < pixels and os.environ.get("FDK_STAGE_FP32") != "1"
         return f"bp_lds_kernel<float, {strip}, {waves}, {cw}, {str(in_place).lower()}>"
