@@ -1246,26 +1246,31 @@ fdk_status fdk_filter_projections(const fdk_filter_geometry* g, const float* src
     a.W = g->width;
     a.H = g->height;
     a.M = f->M;
-    a.maxbits = nullptr;
+    a.wave_max = nullptr;
     if (dtype == FDK_F32) {
         ProfScope ps("filter", s);
         HIP_TRY(launch_filter(a, s));
         return end_call(*d, s);
     }
-    // FP16/BF16 output: the stack is filtered into an FP32 workspace, the
-    // filter raising each projection's maximum as it writes, then packed in
-    // one pass (the maxima need no pass of their own)
-    const size_t n_px = (size_t)g->n_proj * g->height * g->width;
-    hipError_t e = ensure(d->filter_ws, n_px * sizeof(float));
-    if (e == hipSuccess) e = ensure(d->filter_max, (size_t)g->n_proj * sizeof(unsigned));
+    // FP16/BF16 output: the stack is filtered into an FP32 workspace, each
+    // wave recording the largest magnitude it wrote; one small kernel takes
+    // the maximum per projection and one pass packs the stack.  (Filtering in
+    // chunks through a ring that stays in the memory-side cache measured
+    // slower: the chunk boundaries cost more than the cached re-read saves.)
+    const int64_t per = (int64_t)g->height * g->width;
+    const int64_t wave_per = (int64_t)((g->height + 1) / 2) * kFilterWaves;
+    hipError_t e = ensure(d->filter_ws, (size_t)g->n_proj * per * sizeof(float));
+    if (e == hipSuccess)
+        e = ensure(d->filter_max, (size_t)g->n_proj * (wave_per * sizeof(float) + sizeof(unsigned)));
     if (e != hipSuccess) return fail(FDK_E_NOMEM, "filter workspace: %s", hipGetErrorString(e));
-    unsigned* maxbits = static_cast<unsigned*>(d->filter_max.p);
-    HIP_TRY(launch_zero_u32(maxbits, g->n_proj, s));
+    float* wave_max = static_cast<float*>(d->filter_max.p);
+    unsigned* maxbits = reinterpret_cast<unsigned*>(wave_max + (size_t)g->n_proj * wave_per);
     a.dst = static_cast<float*>(d->filter_ws.p);
-    a.maxbits = maxbits;
+    a.wave_max = wave_max;
     {
         ProfScope ps("filter", s);
         HIP_TRY(launch_filter(a, s));
+        HIP_TRY(launch_filter_max(a, maxbits, s));
     }
     {
         ProfScope ps("pack", s);

@@ -31,6 +31,7 @@ namespace fdk {
 namespace {
 
 constexpr int kFilterThreads = 1024;
+static_assert(kFilterThreads == 64 * kFilterWaves, "one per-wave maximum per wave");
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
@@ -174,19 +175,28 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(FilterArgs f)
         if (has1) d1[i] = r1;
         m = fmaxf(m, fmaxf(fabsf(r0), fabsf(r1)));
     }
-    if (f.maxbits != nullptr) {
-        // the largest magnitude of the two rows, into the projection's maximum
-        // (the packing pass that follows needs it); the spectrum buffer is free now
-        float* red = reinterpret_cast<float*>(lds2);
+    if (f.wave_max != nullptr) {
+        // the largest magnitude this wave wrote, for the packing pass that
+        // follows (one plain store per wave: no barrier, no atomics)
         for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int w = 1; w < kFilterThreads / 64; ++w) m = fmaxf(m, red[w]);
-            atomicMax(f.maxbits + k, __float_as_uint(m));
-        }
+        if ((threadIdx.x & 63) == 0)
+            f.wave_max[((int64_t)k * pairs + (j0 >> 1)) * kFilterWaves + (threadIdx.x >> 6)] = m;
     }
+}
+
+// One workgroup per projection: the largest of its per-wave maxima, as bits
+// (non-negative floats order like their bits).
+__global__ __launch_bounds__(256) void filter_max_kernel(const float* __restrict__ wave_max, int per_proj,
+                                                         unsigned* __restrict__ maxbits)
+{
+    __shared__ float red[4];
+    const float* p = wave_max + (int64_t)blockIdx.x * per_proj;
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < per_proj; i += 256) m = fmaxf(m, p[i]);
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) maxbits[blockIdx.x] = __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
 }
 
 }  // namespace
@@ -205,6 +215,14 @@ hipError_t launch_filter(const FilterArgs& f, hipStream_t s)
         attr_set = true;
     }
     hipLaunchKernelGGL(filter_kernel, dim3((unsigned)blocks), dim3(kFilterThreads), lds, s, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_max(const FilterArgs& f, unsigned* maxbits, hipStream_t s)
+{
+    if (f.wave_max == nullptr || f.n_proj < 1) return hipErrorInvalidValue;
+    const int per = ((f.H + 1) / 2) * kFilterWaves;
+    hipLaunchKernelGGL(filter_max_kernel, dim3((unsigned)f.n_proj), dim3(256), 0, s, f.wave_max, per, maxbits);
     return hipGetLastError();
 }
 

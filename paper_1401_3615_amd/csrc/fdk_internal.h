@@ -136,10 +136,13 @@ struct FilterArgs {
                                  // order the in-place FFT leaves the spectrum
     const double2* tw;           // M / 4 twiddles exp(-2 pi i t / M)
     int32_t n_proj, W, H, M;     // M: power of two >= 2 W - 1, 1.25 M FP64 complex fit 80 KiB of LDS
-    unsigned* maxbits;           // or null: bits of max |dst| per projection, raised by atomicMax
-                                 // (non-negative floats order like their bits)
+    float* wave_max;             // or null: max |dst| of each wave's share of a row pair, at
+                                 // ((k * pairs) + pair) * kFilterWaves + wave, pairs = (H + 1) / 2
 };
+constexpr int kFilterWaves = 16;   // waves per filter workgroup
 hipError_t launch_filter(const FilterArgs& f, hipStream_t s);
+// maxbits[k] = bits of the largest wave_max entry of projection k (k < f.n_proj)
+hipError_t launch_filter_max(const FilterArgs& f, unsigned* maxbits, hipStream_t s);
 
 // Iterative solvers (fdk_iter.hip).  Reductions write one FP64 partial per
 // workgroup of a fixed grid of kRedBlocks; scalar_kernel combines them and
@@ -196,7 +199,6 @@ hipError_t launch_unstage_add(const float* padded, float* out, int n, int W, int
                               uint64_t stride_elems, int accumulate, hipStream_t s);
 hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* dst, float* scale,
                        hipStream_t s);
-hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 // FP16/BF16 packing of n projections whose max |src| bits are known (maxbits):
 // dst and scale as fdk_pack_projections
 hipError_t launch_pack_known_max(const float* src, int n, int W, int H, int dtype, void* dst, const unsigned* maxbits,

@@ -350,13 +350,6 @@ hipError_t launch_pack_known_max(const float* src, int n, int W, int H, int dtyp
     return hipGetLastError();
 }
 
-hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
-    return hipGetLastError();
-}
-
 hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* dst, float* scale,
                        hipStream_t s)
 {

@@ -88,12 +88,12 @@ def test_filter_full_detector_rows(fdk):
 
 
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
-@pytest.mark.parametrize("n,h,w", [(5, 9, 200), (7, 9, 201), (96, 64, 320)])
+@pytest.mark.parametrize("n,h,w", [(5, 9, 200), (7, 9, 201), (96, 64, 320), (75, 33, 130)])
 def test_filter_packed_output(fdk, dtype, n, h, w):
-    """FP16/BF16 output equals packing the FP32 output.  Each projection is
-    packed by the workgroup that completes its rows: odd row counts, a
-    projection size that is not a multiple of four, and many projections
-    whose row pairs run on every XCD."""
+    """FP16/BF16 output equals packing the FP32 output (scale from the
+    per-wave maxima the filter records): odd row counts, a projection size
+    that is not a multiple of four or of eight, and many projections whose
+    row pairs run on every XCD."""
     carm = S.CArm(n, w, h, pixel=400.0 / w)
     fg = fgeom_of(fdk, carm)
     li = torch.randn(n, h, w, generator=torch.Generator().manual_seed(7)).to(DEV)
