@@ -667,6 +667,11 @@ TileArgs make_args(const fdk_volume* v, const fdk_projections* p, int esize, Til
 // the windows, then (at a 256-byte boundary) the set-ups.
 size_t anc_offset(uint64_t n) { return (size_t)((n * sizeof(Win) + 255) / 256 * 256); }
 size_t window_table_bytes(uint64_t n) { return anc_offset(n) + (size_t)n * sizeof(Anc); }
+// the anchor records of a batch's window table of n entries
+Anc* batch_anchors(BatchEntry& b, uint64_t n)
+{
+    return reinterpret_cast<Anc*>(static_cast<unsigned char*>(b.windows.p) + anc_offset(n));
+}
 
 fdk_status check_grid(const TileArgs& a)
 {
@@ -1832,6 +1837,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         stages.reserve(n_scans);
         std::vector<int32_t> item_begin(n_scans + 1);
         std::vector<float> out_scales(n_scans);
+        std::vector<int> const_ws(n_scans);
         std::vector<int> proj_begin(n_scans);
         std::vector<int64_t> win_off(n_scans);   // window table offset (layout 3) or -1
         uint64_t win_total = 0;
@@ -1848,6 +1854,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
             for (int k = 0; k < sc.proj.n_proj; ++k)
                 scale_ptrs.push_back(sc.proj.scale ? sc.proj.scale + k : nullptr);
             out_scales[j] = c.out_scale;
+            const_ws[j] = c.const_w;
             const int es = esize_of(sc.proj.dtype);
             TileShape ts = t;
             ts.layout = scan_layout(&sc.proj);
@@ -1878,7 +1885,7 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         alloc(b.coef64, coef64.size() * sizeof(double));
         alloc(b.coef_dev, (size_t)total_proj * 16 * sizeof(double));
         alloc(b.counter, sizeof(unsigned));
-        if (win_total > 0) alloc(b.windows, win_total * sizeof(Win));
+        if (win_total > 0) alloc(b.windows, window_table_bytes(win_total));
         if (e != hipSuccess) {
             release_entry(b);
             return fail(FDK_E_NOMEM, "batched tables: %s", hipGetErrorString(e));
@@ -1891,8 +1898,14 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
                                  static_cast<unsigned char*>(d->batch_staged.p) + stage_off[j],
                                  static_cast<double*>(b.coef_dev.p) + (size_t)proj_begin[j] * 16, sc.volume,
                                  out_scales[j], accumulate, sc.proj.dtype);
-            // the persistent kernel anchors every lane itself (no set-up table)
-            if (win_off[j] >= 0) tiles[j].win = static_cast<const Win*>(b.windows.p) + win_off[j];
+            // LDS scans: the windows and the tile anchors of every (tile,
+            // projection); circular orbits (u and w constant along z) take
+            // the column walk
+            tiles[j].const_w = const_ws[j];
+            if (win_off[j] >= 0) {
+                tiles[j].win = static_cast<const Win*>(b.windows.p) + win_off[j];
+                tiles[j].anc = batch_anchors(b, win_total) + win_off[j];
+            }
             if (is_raw(&sc.proj)) {   // the caller's unpadded images, row pitch W
                 const uint64_t img = (uint64_t)sc.proj.width * sc.proj.height * 4;
                 tiles[j].proj = static_cast<const unsigned char*>(sc.proj.data);
@@ -1914,8 +1927,12 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
         if (e == hipSuccess && d->capture_stream == nullptr)
             e = hipStreamCreateWithFlags(&d->capture_stream, hipStreamNonBlocking);
         // capture: stage every stack, fold the scales, reset the queue, run the persistent kernel
+        // (its column-walk-only form when every scan is an FP32 LDS scan on a circular orbit)
+        int circular = 1;
+        for (int j = 0; j < n_scans; ++j)
+            circular &= (int)(tiles[j].dtype == FDK_F32 && tiles[j].layout == 3 && const_ws[j] == 2);
         hipGraph_t graph = nullptr;
-        const int per_cu = batched_blocks_per_cu(t.strip, t.waves);
+        const int per_cu = batched_blocks_per_cu(t.strip, t.waves, circular);
         int grid = std::max(1, d->num_cus * std::max(1, per_cu));
         if ((int64_t)grid > items) grid = (int)items;
         if (e == hipSuccess) e = hipStreamBeginCapture(d->capture_stream, hipStreamCaptureModeThreadLocal);
@@ -1930,13 +1947,13 @@ fdk_status fdk_backproject_batched(const fdk_scan* scans, int32_t n_scans, int a
             for (int j = 0; j < n_scans && ew == hipSuccess; ++j)
                 if (win_off[j] >= 0)
                     ew = launch_window(tiles[j], t.strip, t.waves, static_cast<Win*>(b.windows.p) + win_off[j],
-                                       nullptr, d->capture_stream);
+                                       batch_anchors(b, win_total) + win_off[j], d->capture_stream);
             if (e2 == hipSuccess) e2 = ew;
             hipError_t e3 = launch_reset_counter(static_cast<unsigned*>(b.counter.p), d->capture_stream);
             hipError_t e4 = launch_bp_batched(static_cast<const TileArgs*>(b.tiles.p),
                                               static_cast<const int32_t*>(b.item_begin.p), n_scans,
                                               static_cast<unsigned*>(b.counter.p), (int)items, grid,
-                                              t.strip, t.waves, d->capture_stream);
+                                              t.strip, t.waves, circular, d->capture_stream);
             hipError_t ec = hipStreamEndCapture(d->capture_stream, &graph);
             e = e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3 != hipSuccess ? e3 : e4 != hipSuccess ? e4 : ec;
         }

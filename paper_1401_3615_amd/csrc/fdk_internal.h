@@ -186,9 +186,11 @@ hipError_t launch_bp(const TileArgs& a, int strip, int waves, hipStream_t s);
 // the windows of that tile shape.
 hipError_t launch_bp_lanes(const TileArgs& a, hipStream_t s);
 hipError_t launch_fp(const TileArgs& a, int strip, int waves, hipStream_t s);
+// circular: every scan is FP32, sampled from LDS windows, with const_w == 2
+// (the persistent kernel that holds only the column walk)
 hipError_t launch_bp_batched(const TileArgs* dev_scans, const int32_t* dev_item_begin, int n_scans,
                              unsigned* dev_counter, int total_items, int grid, int strip, int waves,
-                             hipStream_t s);
+                             int circular, hipStream_t s);
 hipError_t launch_reset_counter(unsigned* counter, hipStream_t s);
 hipError_t launch_fill(float* p, uint64_t n, float value, hipStream_t s);
 // rows [j0[k], j0[k] + rows) of each of n device images of H rows of row_bytes
@@ -208,6 +210,6 @@ hipError_t launch_pack_known_max(const float* src, int n, int W, int H, int dtyp
 // with the given tile shape.
 hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, Anc* anc, hipStream_t s);
 int supported_tile(int strip, int waves);
-int batched_blocks_per_cu(int strip, int waves);
+int batched_blocks_per_cu(int strip, int waves, int circular);
 
 }  // namespace fdk

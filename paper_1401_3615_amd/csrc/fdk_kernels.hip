@@ -731,8 +731,10 @@ constexpr int lds_waves_per_eu()
 }
 
 // The persistent batched kernel holds every sampling path (gathers from the
-// three staged layouts, LDS windows of the three dtypes): its own budget.
-template <int S> constexpr int batched_waves_per_eu() { return S <= 2 ? 5 : S <= 8 ? 4 : 3; }
+// three staged layouts, LDS windows of the three dtypes, each with the
+// column walk and the per-voxel walk): its own budget, from the compiled
+// register counts (32-plane strips need more than three waves allow).
+template <int S> constexpr int batched_waves_per_eu() { return S <= 2 ? 5 : S <= 8 ? 4 : S <= 16 ? 3 : 2; }
 
 // The window of one projection as the LDS tile holds it: 4-pixel chunks
 // [c_lo, c_hi] x [j0, j1] of the staged image, in rows `pitch` pixels apart.
@@ -891,9 +893,10 @@ __device__ __forceinline__ Anc load_anc(const Anc* p)
 __device__ __forceinline__ void wait_vm_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // One tile of the LDS backprojection; `lds` is the workgroup's 32 KiB tile.
-// CWM: 1 every projection has w constant along z (one 1/w per strip), 0 none
-// is assumed to, 2 decided per projection (the persistent kernel, whose scans
-// differ).
+// CWM: 3 every projection has u and w constant along z (the column walk), 1
+// w constant (one 1/w per strip), 0 none is assumed to, all three from the
+// tile anchors; 2 per-lane anchors from the coefficients, the walk decided
+// per projection (for launches without an anchor table).
 // Bilinear sample of an unpadded FP32 image at (anchor + (dx, dy)), zero off
 // the detector; out of line (see the caller).
 __device__ __attribute__((noinline)) float raw_sample(const unsigned char* img, uint32_t bytes, float dx, float dy,
@@ -1156,6 +1159,18 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     }
 }
 
+// One LDS tile of a scan in the persistent kernel, from the scan's tile
+// anchors: the column walk when its orbit keeps u and w constant along z (a
+// circular orbit about z, a.const_w == 2), otherwise the per-voxel walk.
+// (Two bodies per storage type: with a third, the constant-w walk, the
+// persistent kernel's registers spill at 32-plane strips.)
+template <typename T, int S, int NW, bool RAWOK>
+__device__ __forceinline__ void lds_tile_by_walk(const TileArgs& a, int tile, int rot_div, float* lds)
+{
+    if (a.const_w == 2) bp_lds_tile<T, S, NW, 3, RAWOK>(a, tile, rot_div, lds);
+    else bp_lds_tile<T, S, NW, 0, RAWOK>(a, tile, rot_div, lds);
+}
+
 template <typename T, int S, int NW, int CWM, bool RAWOK = false>
 __global__ __launch_bounds__(kWave * NW)
     __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu<S, NW, CWM, RAWOK, sizeof(T) == 2>(),
@@ -1168,10 +1183,17 @@ __global__ __launch_bounds__(kWave * NW)
 // Persistent backprojection over many scans: every workgroup pulls
 // (scan, tile) items from a queue until it is empty.  Items are ordered by
 // decreasing cost (projection count) on the host, so the tail is made of the
-// cheapest tiles.
-template <int S, int NW>
+// cheapest tiles.  CIRC: every scan is FP32, sampled from LDS windows, on a
+// circular orbit about z; the kernel then holds only the column walk and
+// runs at that body's occupancy.
+template <int S, int NW, bool CIRC>
+constexpr int batched_waves()
+{
+    return CIRC ? lds_waves_per_eu<S, NW, 3, true, false>() : batched_waves_per_eu<S>();
+}
+template <int S, int NW, bool CIRC = false>
 __global__ __launch_bounds__(kWave * NW)
-    __attribute__((amdgpu_waves_per_eu(batched_waves_per_eu<S>(), batched_waves_per_eu<S>()))) void bp_batched_kernel(const TileArgs* __restrict__ scans,
+    __attribute__((amdgpu_waves_per_eu(batched_waves<S, NW, CIRC>(), batched_waves<S, NW, CIRC>()))) void bp_batched_kernel(const TileArgs* __restrict__ scans,
                                                                 const int32_t* __restrict__ item_begin,
                                                                 int n_scans, unsigned* counter,
                                                                 int total_items)
@@ -1191,10 +1213,12 @@ __global__ __launch_bounds__(kWave * NW)
         }
         const TileArgs a = scans[lo];
         const int tile = item - item_begin[lo];
-        if (a.layout == 3) {
-            if (a.dtype == 1) bp_lds_tile<__half, S, NW, 2>(a, tile, (int)gridDim.x, lds);
-            else if (a.dtype == 2) bp_lds_tile<bf16_t, S, NW, 2>(a, tile, (int)gridDim.x, lds);
-            else bp_lds_tile<float, S, NW, 2, true>(a, tile, (int)gridDim.x, lds);
+        if constexpr (CIRC) {
+            bp_lds_tile<float, S, NW, 3, true>(a, tile, (int)gridDim.x, lds);
+        } else if (a.layout == 3) {
+            if (a.dtype == 1) lds_tile_by_walk<__half, S, NW, false>(a, tile, (int)gridDim.x, lds);
+            else if (a.dtype == 2) lds_tile_by_walk<bf16_t, S, NW, false>(a, tile, (int)gridDim.x, lds);
+            else lds_tile_by_walk<float, S, NW, true>(a, tile, (int)gridDim.x, lds);
         } else {
             bp_tile_any<S, NW>(a, tile, (int)gridDim.x);
         }
@@ -1635,21 +1659,25 @@ hipError_t fp_dispatch_t(const TileArgs& a, int nblocks, hipStream_t st)
 
 template <int S, int NW>
 hipError_t batched_dispatch_t(const TileArgs* scans, const int32_t* ib, int n, unsigned* c, int total,
-                              int grid, hipStream_t st)
+                              int grid, bool circ, hipStream_t st)
 {
-    hipLaunchKernelGGL((bp_batched_kernel<S, NW>), dim3(grid), dim3(kWave * NW), 0, st, scans, ib, n, c,
-                       total);
+    if (circ)
+        hipLaunchKernelGGL((bp_batched_kernel<S, NW, true>), dim3(grid), dim3(kWave * NW), 0, st, scans, ib, n,
+                           c, total);
+    else
+        hipLaunchKernelGGL((bp_batched_kernel<S, NW, false>), dim3(grid), dim3(kWave * NW), 0, st, scans, ib, n,
+                           c, total);
     return hipGetLastError();
 }
 
 template <int S, int NW>
-int batched_occupancy_t()
+int batched_occupancy_t(bool circ)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched_kernel<S, NW>, kWave * NW, 0) !=
-        hipSuccess)
-        return 0;
-    return nb;
+    const hipError_t e =
+        circ ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched_kernel<S, NW, true>, kWave * NW, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, bp_batched_kernel<S, NW, false>, kWave * NW, 0);
+    return e == hipSuccess ? nb : 0;
 }
 
 #define FDK_TILE_TABLE(X) \
@@ -1693,19 +1721,20 @@ hipError_t launch_fp(const TileArgs& a, int strip, int waves, hipStream_t s)
 }
 
 hipError_t launch_bp_batched(const TileArgs* scans, const int32_t* item_begin, int n_scans,
-                             unsigned* counter, int total_items, int grid, int strip, int waves,
+                             unsigned* counter, int total_items, int grid, int strip, int waves, int circular,
                              hipStream_t s)
 {
-#define X(S, W) \
-    if (strip == S && waves == W) return batched_dispatch_t<S, W>(scans, item_begin, n_scans, counter, total_items, grid, s);
+#define X(S, W)                                                                                              \
+    if (strip == S && waves == W)                                                                            \
+        return batched_dispatch_t<S, W>(scans, item_begin, n_scans, counter, total_items, grid, circular != 0, s);
     FDK_TILE_TABLE(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
-int batched_blocks_per_cu(int strip, int waves)
+int batched_blocks_per_cu(int strip, int waves, int circular)
 {
-#define X(S, W) if (strip == S && waves == W) return batched_occupancy_t<S, W>();
+#define X(S, W) if (strip == S && waves == W) return batched_occupancy_t<S, W>(circular != 0);
     FDK_TILE_TABLE(X)
 #undef X
     return 0;
