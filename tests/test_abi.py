@@ -185,6 +185,8 @@ def test_adjoint_tiles(fdk):
         assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == good
     fdk.set_tile(fdk.TUNE_ADJOINT, 0, 0)
     assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == (60, 1, 4)
+    # large volumes: two projections per workgroup on 36-row tiles
+    assert fdk.get_tile(fdk.Volume(512, 0.5), fdk.TUNE_ADJOINT) == (36, 2, 4)
 
 
 def test_batched_slot(fdk):

@@ -170,3 +170,38 @@ def test_1024_fp16_rowband_sampled(fdk, c1):
     check_points(out, xyz, ref, "1024^3 fp16 total error", rel=1e-3)
     del out, qp
     torch.cuda.empty_cache()
+
+
+def test_512_adjoint_whole_projections(fdk, c1):
+    """The 512^3 adjoint in the launch configuration the benchmark times
+    (detector tiles of 36 rows, two projections per workgroup), applied to
+    the backprojection of the phantom: whole projection images against the
+    oracle's scatter for the first, a middle and the last projection; then
+    the dot test <B q, x> = <q, B^T x> with a seeded Gaussian x."""
+    carm, mats, q, q64 = c1
+    L, voxel = 512, 0.5
+    geom, vol = fdk.Geometry(mats, carm.width, carm.height), fdk.Volume(L, voxel)
+    assert fdk.get_tile(vol, fdk.TUNE_ADJOINT) == (36, 2, 4)
+    x = fdk.backproject(q, geom, vol)
+    out = fdk.forwardproject(x, geom, vol)
+    torch.cuda.synchronize()
+    x64 = x.double().cpu().numpy()
+    for k in (0, 247, 495):
+        ref = oracle.forwardproject(L, voxel, mats[k:k + 1], x64, carm.width, carm.height)[0]
+        got = out[k].double().cpu().numpy()
+        assert np.linalg.norm(ref) > 0
+        err = oracle.rel_l2(got, ref)
+        print(f"512^3 adjoint projection {k}: rel L2 {err:.3e}")
+        assert err <= REL_L2_FP32
+    del out, x64
+    g = torch.Generator(device=DEV)
+    g.manual_seed(21)
+    xr = torch.randn(L, L, L, device=DEV, generator=g)
+    lhs = float((x.double() * xr.double()).sum())
+    btx = fdk.forwardproject(xr, geom, vol)
+    rhs = float((q.double() * btx.double()).sum())
+    scale = float(x.double().norm() * xr.double().norm())
+    print(f"512^3 dot test rel {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) <= 1e-5 * scale
+    del btx, xr, x
+    torch.cuda.empty_cache()
