@@ -128,6 +128,50 @@ __device__ __forceinline__ void dif_reverse(double2* x, const double2* tw, int M
     }
 }
 
+// Radix-4 stages of dif() for block sizes hi, hi / 4, ..., lo (lo >= 4).
+__device__ __forceinline__ void dif_stages(double2* x, const double2* tw, int M, int hi, int lo)
+{
+    const int q = M >> 2;
+    for (int Bs = hi; Bs >= lo; Bs >>= 2) {
+        const int L = Bs >> 2, s = M / Bs;
+        for (int t = threadIdx.x; t < q; t += kFilterThreads) {
+            const int i = t & (L - 1), b0 = (t - i) << 2;
+            double2* p = x + b0 + i;
+            double2 x0 = p[0], x1 = p[L], x2 = p[2 * L], x3 = p[3 * L];
+            dft4(x0, x1, x2, x3);
+            const double2 w = tw[i * s];
+            const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
+            p[0] = x0;
+            p[L] = cmul(x1, w);
+            p[2 * L] = cmul(x2, w2);
+            p[3 * L] = cmul(x3, w3);
+        }
+        __syncthreads();
+    }
+}
+
+// Radix-4 stages of dif_reverse() for block sizes lo, 4 lo, ..., hi.
+__device__ __forceinline__ void dif_reverse_stages(double2* x, const double2* tw, int M, int lo, int hi)
+{
+    const int q = M >> 2;
+    for (int Bs = lo; Bs <= hi; Bs <<= 2) {
+        const int L = Bs >> 2, s = M / Bs;
+        for (int t = threadIdx.x; t < q; t += kFilterThreads) {
+            const int i = t & (L - 1), b0 = (t - i) << 2;
+            double2* p = x + b0 + i;
+            const double2 w = tw[i * s];
+            const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
+            double2 x0 = p[0], x1 = cmul(p[L], w), x2 = cmul(p[2 * L], w2), x3 = cmul(p[3 * L], w3);
+            dft4(x0, x1, x2, x3);
+            p[0] = x0;
+            p[L] = x1;
+            p[2 * L] = x2;
+            p[3 * L] = x3;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(kFilterThreads) void filter_kernel(FilterArgs f)
 {
     extern __shared__ double2 lds2[];   // M complex values + M/4 twiddles
@@ -145,35 +189,98 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(FilterArgs f)
     const double* c0 = f.wc + (int64_t)j0 * f.W;
     const double* c1 = c0 + f.W;
     const double* wp = f.wp + (int64_t)k * f.W;
-    for (int i = threadIdx.x; i < M; i += kFilterThreads) {
+    // weighted input of the two rows at i (zero padding from W on)
+    auto in = [&](int i) {
         double x0 = 0.0, x1 = 0.0;
         if (i < f.W) {
             const double w = wp[i];
             x0 = (double)s0[i] * c0[i] * w;
             if (has1) x1 = (double)s1[i] * c1[i] * w;
         }
-        x[i] = make_double2(x0, x1);
-    }
-    __syncthreads();
-    dif(x, tws, M, odd);
-    // conj(Z H) in the digit-reversed order of the spectrum (hs is stored so)
-    for (int m = threadIdx.x; m < M; m += kFilterThreads) {
-        const double h = f.hs[m];
-        const double2 v = x[m];
-        x[m] = make_double2(v.x * h, -v.y * h);
-    }
-    __syncthreads();
-    dif_reverse(x, tws, M, odd);
+        return make_double2(x0, x1);
+    };
     // the conjugate of the result: row 0 real part, row 1 minus imaginary part
     float* d0 = f.dst + ((int64_t)k * f.H + j0) * f.W;
     float* d1 = d0 + f.W;
     float m = 0.0f;
-    for (int i = threadIdx.x; i < f.W; i += kFilterThreads) {
-        const double2 v = x[i];
+    auto out = [&](int i, double2 v) {
         const float r0 = (float)v.x, r1 = has1 ? (float)-v.y : 0.0f;
         d0[i] = r0;
         if (has1) d1[i] = r1;
         m = fmaxf(m, fmaxf(fabsf(r0), fabsf(r1)));
+    };
+    const int q = M >> 2, h = M >> 1;
+    if (M < 16) {
+        // tiny transforms: every stage on its own
+        for (int i = threadIdx.x; i < M; i += kFilterThreads) x[i] = in(i);
+        __syncthreads();
+        dif(x, tws, M, odd);
+        for (int i = threadIdx.x; i < M; i += kFilterThreads) {
+            const double hv = f.hs[i];
+            const double2 v = x[i];
+            x[i] = make_double2(v.x * hv, -v.y * hv);
+        }
+        __syncthreads();
+        dif_reverse(x, tws, M, odd);
+        for (int i = threadIdx.x; i < f.W; i += kFilterThreads) out(i, x[i]);
+    } else {
+        // first stage fused with the input weighting: the padded input is zero
+        // from W <= M / 2 on, so the legs at M / 2 and 3 M / 4 are zero (the
+        // twiddles come from the global table: the LDS copy is not synced yet)
+        if (odd) {
+            for (int j = threadIdx.x; j < h; j += kFilterThreads) {
+                const double2 a = in(j);
+                x[j] = a;
+                x[j + h] = cmul(a, twiddle_half(f.tw, j, q));
+            }
+        } else {
+            for (int t = threadIdx.x; t < q; t += kFilterThreads) {
+                const double2 x0 = in(t), x1 = in(t + q);
+                const double2 d = make_double2(x1.y, -x1.x);   // -i x1
+                const double2 w = f.tw[t];
+                const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
+                x[t] = make_double2(x0.x + x1.x, x0.y + x1.y);
+                x[t + q] = cmul(make_double2(x0.x + d.x, x0.y + d.y), w);
+                x[t + 2 * q] = cmul(make_double2(x0.x - x1.x, x0.y - x1.y), w2);
+                x[t + 3 * q] = cmul(make_double2(x0.x - d.x, x0.y - d.y), w3);
+            }
+        }
+        __syncthreads();
+        dif_stages(x, tws, M, odd ? h : q, 16);
+        // the last forward stage (blocks of four, unit twiddles), conj(Z H) in
+        // the digit-reversed order of the spectrum (hs is stored so) and the
+        // first inverse stage, on the four values each thread holds
+        for (int t = threadIdx.x; t < q; t += kFilterThreads) {
+            double2* p = x + 4 * t;
+            double2 v[4] = {p[0], p[1], p[2], p[3]};
+            dft4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double hv = f.hs[4 * t + r];
+                v[r] = make_double2(v[r].x * hv, -v[r].y * hv);
+            }
+            dft4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) p[r] = v[r];
+        }
+        __syncthreads();
+        dif_reverse_stages(x, tws, M, 16, odd ? h : q);
+        // last inverse stage fused with the output: only the first W values
+        if (odd) {
+            for (int j = threadIdx.x; j < f.W; j += kFilterThreads) {
+                const double2 a = x[j], b = cmul(x[j + h], twiddle_half(tws, j, q));
+                out(j, make_double2(a.x + b.x, a.y + b.y));
+            }
+        } else {
+            for (int t = threadIdx.x; t < q && t < f.W; t += kFilterThreads) {
+                const double2 w = tws[t];
+                const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
+                double2 x0 = x[t], x1 = cmul(x[t + q], w), x2 = cmul(x[t + 2 * q], w2), x3 = cmul(x[t + 3 * q], w3);
+                dft4(x0, x1, x2, x3);
+                out(t, x0);
+                if (t + q < f.W) out(t + q, x1);
+            }
+        }
     }
     if (f.wave_max != nullptr) {
         // the largest magnitude this wave wrote, for the packing pass that

@@ -206,8 +206,8 @@ hipError_t launch_pack(const float* src, int n, int W, int H, int dtype, void* d
 hipError_t launch_pack_known_max(const float* src, int n, int W, int H, int dtype, void* dst, const unsigned* maxbits,
                                  float* scale, hipStream_t s);
 // Windows (out) and sampling set-ups (anc, n_tiles x n_proj each; null: none,
-// for the persistent kernel, which anchors every lane itself) of an LDS launch
-// with the given tile shape.
+// for launches whose lanes anchor themselves from the coefficients) of an LDS
+// launch with the given tile shape.
 hipError_t launch_window(const TileArgs& a, int strip, int waves, Win* out, Anc* anc, hipStream_t s);
 int supported_tile(int strip, int waves);
 int batched_blocks_per_cu(int strip, int waves, int circular);
