@@ -13,8 +13,13 @@
 // kernel spectrum is multiplied in that order (the host stores it permuted),
 // and the inverse runs the same stages in reverse order, each twiddling its
 // inputs before the butterfly, on the conjugated data (the inverse of the
-// stage product, up to 1/M and conjugation).  One buffer of M complex values
-// plus the twiddles is 80 KiB at M = 4096, so two workgroups share a CU.  The
+// stage product, up to 1/M and conjugation).  From M = 16 on, the passes at
+// the ends and in the middle are fused: the input weighting is the first
+// stage (whose legs from M/2 on are zero padding), the last forward stage,
+// the spectrum product and the first inverse stage run on the four values a
+// thread holds, and the last inverse stage writes the W outputs.  One buffer
+// of M complex values plus the twiddles is 80 KiB at M = 4096, so two
+// workgroups share a CU.  The
 // weights, the permuted kernel spectrum (with the output gain and 1/M folded
 // in) and the twiddles come from FP64 tables computed on the host.
 //

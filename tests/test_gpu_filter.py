@@ -44,10 +44,14 @@ def oracle_filter(fg, li, rows=None):
 
 
 @pytest.mark.parametrize("W,H,N,fan_sign", [(101, 7, 5, -1.0), (64, 6, 4, 1.0), (33, 1, 3, -1.0),
-                                            (2, 3, 3, -1.0), (1, 4, 3, 1.0), (257, 5, 3, -1.0)])
+                                            (2, 3, 3, -1.0), (1, 4, 3, 1.0), (257, 5, 3, -1.0),
+                                            (3, 2, 3, -1.0), (7, 3, 3, 1.0), (12, 3, 3, -1.0),
+                                            (20, 2, 3, 1.0), (1000, 3, 3, -1.0)])
 def test_filter_matches_oracle(fdk, W, H, N, fan_sign):
-    """Ragged widths (FFT sizes 4 .. 1024), odd row counts (the last row of
-    a projection filtered alone), both fan orientations."""
+    """Ragged widths (FFT sizes 4 .. 2048: the small sizes that run every
+    stage on its own, 4 and 8, and the fused first and last stages from 16
+    up, with log2 M even and odd), odd row counts (the last row of a
+    projection filtered alone), both fan orientations."""
     carm = S.CArm(N, W, H, pixel=max(0.308, 400.0 / W))
     fg = fgeom_of(fdk, carm, fan_sign)
     li = np.random.default_rng(W + H).standard_normal((N, H, W)).astype(np.float32)
