@@ -1074,11 +1074,15 @@ double parker(double beta, double gamma, double range)
     return s * s;
 }
 
+// Circular length of the row filter: the shortest 2^k or 5 * 2^k (k >= 2)
+// of at least 2 W - 1 (1248-pixel rows: 2560 instead of 4096).
 int filter_size(int W)
 {
     int M = 4;
     while (M < 2 * W - 1) M <<= 1;
-    return M;
+    int M5 = 20;
+    while (M5 < 2 * W - 1) M5 <<= 1;
+    return std::min(M, M5);
 }
 
 fdk_status check_filter(const fdk_filter_geometry* g)
@@ -1130,9 +1134,16 @@ std::string filter_key(const fdk_filter_geometry* g)
 // d + r f'(p').
 std::vector<int> dif_order(int M)
 {
+    // the kernel's stages: radix 5 first when 5 divides M, then radix 2 when
+    // the power of two left has an odd exponent, then radix 4
     std::vector<int> radix;
+    int m = M;
+    if (m % 5 == 0) {
+        radix.push_back(5);
+        m /= 5;
+    }
     int lg = 0;
-    while ((1 << lg) < M) ++lg;
+    while ((1 << lg) < m) ++lg;
     if (lg & 1) radix.push_back(2);
     for (int i = 0; i < lg / 2; ++i) radix.push_back(4);
     std::vector<int> order(M);

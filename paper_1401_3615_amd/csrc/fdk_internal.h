@@ -135,7 +135,7 @@ struct FilterArgs {
     const double* hs;            // M: real spectrum of the circular ramp kernel x gain / M, in the
                                  // order the in-place FFT leaves the spectrum
     const double2* tw;           // M / 4 twiddles exp(-2 pi i t / M)
-    int32_t n_proj, W, H, M;     // M: power of two >= 2 W - 1, 1.25 M FP64 complex fit 80 KiB of LDS
+    int32_t n_proj, W, H, M;     // M: 2^k or 5 * 2^k >= 2 W - 1, 1.25 M FP64 complex fit 80 KiB of LDS
     float* wave_max;             // or null: max |dst| of each wave's share of a row pair, at
                                  // ((k * pairs) + pair) * kFilterWaves + wave, pairs = (H + 1) / 2
 };

@@ -48,10 +48,11 @@ def oracle_filter(fg, li, rows=None):
                                             (3, 2, 3, -1.0), (7, 3, 3, 1.0), (12, 3, 3, -1.0),
                                             (20, 2, 3, 1.0), (1000, 3, 3, -1.0)])
 def test_filter_matches_oracle(fdk, W, H, N, fan_sign):
-    """Ragged widths (FFT sizes 4 .. 2048: the small sizes that run every
-    stage on its own, 4 and 8, and the fused first and last stages from 16
-    up, with log2 M even and odd), odd row counts (the last row of a
-    projection filtered alone), both fan orientations."""
+    """Ragged widths: FFT sizes 2^k from 4 to 2048 (4 and 8 run every stage
+    on its own, from 16 up the first and last stages are fused; log2 M even
+    and odd) and 5 * 2^k (40, 80, 640: a radix-5 first stage, with a radix-2
+    stage after it or not); odd row counts (the last row of a projection
+    filtered alone), both fan orientations."""
     carm = S.CArm(N, W, H, pixel=max(0.308, 400.0 / W))
     fg = fgeom_of(fdk, carm, fan_sign)
     li = np.random.default_rng(W + H).standard_normal((N, H, W)).astype(np.float32)
@@ -72,7 +73,7 @@ def test_filter_without_short_scan_weights(fdk):
 
 
 def test_filter_full_detector_rows(fdk):
-    """1248-pixel rows (FFT size 4096) of the benchmark detector, sampled rows
+    """1248-pixel rows (FFT size 2560 = 5 x 512) of the benchmark detector, sampled rows
     of a full phantom stack (the oracle filters rows independently)."""
     carm = S.CArm(8)
     mats = S.carm_matrices(carm)
