@@ -953,7 +953,7 @@ __device__ __forceinline__ void bp_lds_tile(const TileArgs& a, int tile, int rot
     for (int n = 0; n < a.n_proj; ++n) {
         // this projection's set-up, loaded ahead of the window store so that
         // its latency passes behind the barriers: the tile's anchor record,
-        // or (persistent kernel) the coefficients for per-lane anchors
+        // or (per-lane anchors) the projection's coefficients
         Anc an;
         Coef cur;
         if constexpr (CWM == 2) cur = load_coef(a.coef, po.k);
@@ -1189,7 +1189,9 @@ __global__ __launch_bounds__(kWave * NW)
 template <int S, int NW, bool CIRC>
 constexpr int batched_waves()
 {
-    return CIRC ? lds_waves_per_eu<S, NW, 3, true, false>() : batched_waves_per_eu<S>();
+    // 32-plane strips: the queue loop's registers on top of the column walk's
+    // need more than three waves allow
+    return CIRC ? (S >= 32 && NW >= 4 ? 2 : lds_waves_per_eu<S, NW, 3, true, false>()) : batched_waves_per_eu<S>();
 }
 template <int S, int NW, bool CIRC = false>
 __global__ __launch_bounds__(kWave * NW)

@@ -185,8 +185,10 @@ def test_batched_unstaged_edges_and_large_windows(fdk, strip, waves):
 @pytest.mark.parametrize("layout", [3, 0])
 def test_batched_mixed_orbits(fdk, layout):
     """A batch mixing circular scans (u and w constant along z) with tilted
-    ones (w varies along z): the persistent kernel decides the walk per
-    projection.  Against the oracle and against one launch per scan."""
+    ones (w varies along z): the persistent kernel takes the column walk for
+    the circular scans and the per-voxel walk for the tilted ones (layout 3),
+    or gathers (layout 0).  Against the oracle and against one launch per
+    scan."""
     specs = [(30, 4.0, 9, 128, 96, 0.0, 60), (28, 4.0, 7, 96, 72, 0.4, 61), (24, 5.0, 11, 128, 96, 0.4, 62),
              (32, 3.5, 6, 160, 120, 0.0, 63)]
     scans, refs = [], []
