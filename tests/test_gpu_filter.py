@@ -46,12 +46,12 @@ def oracle_filter(fg, li, rows=None):
 @pytest.mark.parametrize("W,H,N,fan_sign", [(101, 7, 5, -1.0), (64, 6, 4, 1.0), (33, 1, 3, -1.0),
                                             (2, 3, 3, -1.0), (1, 4, 3, 1.0), (257, 5, 3, -1.0),
                                             (3, 2, 3, -1.0), (7, 3, 3, 1.0), (12, 3, 3, -1.0),
-                                            (20, 2, 3, 1.0), (1000, 3, 3, -1.0)])
+                                            (20, 2, 3, 1.0), (1000, 3, 3, -1.0), (10, 3, 3, 1.0)])
 def test_filter_matches_oracle(fdk, W, H, N, fan_sign):
     """Ragged widths: FFT sizes 2^k from 4 to 2048 (4 and 8 run every stage
     on its own, from 16 up the first and last stages are fused; log2 M even
-    and odd) and 5 * 2^k (40, 80, 640: a radix-5 first stage, with a radix-2
-    stage after it or not); odd row counts (the last row of a projection
+    and odd) and 5 * 2^k (20, 40, 80, 640: a radix-5 first stage, with a
+    radix-2 stage after it or not); odd row counts (the last row of a projection
     filtered alone), both fan orientations."""
     carm = S.CArm(N, W, H, pixel=max(0.308, 400.0 / W))
     fg = fgeom_of(fdk, carm, fan_sign)
