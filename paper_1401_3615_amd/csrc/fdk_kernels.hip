@@ -710,7 +710,8 @@ template <int S, int NW> constexpr int lds_cap() { return lds_rows<S>() * lds_pi
 // without spilling (from the compiled register counts): the column walk
 // (CWM 3) over a staged image needs the fewest, the per-voxel walks, the
 // bounds-checked fills of unpadded images (RAWOK) and the per-lane anchors
-// (CWM 2) more; 16-bit windows hold half the prefetched bits.
+// (CWM 2) more; 16-bit windows hold half the prefetched bits (the FP16/BF16
+// column walk at 16 planes fits seven waves, 70 VGPRs; FP32 needs 80).
 template <int S, int NW, int CWM, bool RAWOK, bool HALF>
 constexpr int lds_vgpr_waves()
 {
@@ -718,7 +719,7 @@ constexpr int lds_vgpr_waves()
     if (CWM == 2) return S <= 8 ? 4 : 3;
     const bool lean = CWM == 3 && !RAWOK;
     if (S <= 8) return lean ? 7 : 5;
-    if (S <= 16) return lean ? 6 : (HALF || (CWM == 1 && !RAWOK)) ? 5 : 4;
+    if (S <= 16) return lean ? (HALF ? 7 : 6) : (HALF || (CWM == 1 && !RAWOK)) ? 5 : 4;
     return lean || HALF ? 4 : 3;
 }
 template <int S, int NW, int CWM, bool RAWOK, bool HALF>
