@@ -246,6 +246,9 @@ typedef struct fdk_filter_geometry {
  *   g          host geometry (angles copied before return)
  *   src        DEVICE, n_proj * height * width float32
  *   dst        DEVICE, n_proj * height * width of dtype
+ * Limits: width 1 .. 2048 (one row pair's FP64 spectrum of the circular
+ * length, at most 4096, is held in LDS), n_proj * height * width <= 2^40;
+ * FDK_E_INVALID_ARG beyond them, nothing enqueued.
  * FDK_E_GEOMETRY if R > 0 and d = (R - pi) / 2 is smaller than the largest
  * fan angle of the detector (the short scan does not cover every ray).
  */
