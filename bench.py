@@ -124,8 +124,8 @@ def main() -> int:
                     help="run only warm-up and timed FP32 steps (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(z-slab sharding is a design note only); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(z-slab sharding across GPUs is described, not built); run with --gpus 1", file=sys.stderr)
         return 2
     legs = set() if args.legs == "none" else set(args.legs.split(","))
 
